@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the Floquet-period hot path on one MI355X.
+
+Workload (one "step"): 10 Floquet periods of the L = 30 XYZ-plus-fields chain
+(complex64 state, 8 GiB, plain fused FP32 sweep, T = 0.25, seed 2111) followed
+by one energy-density readout, i.e. the record interval of that run.  Inputs
+are synthetic and resident in HBM before timing starts.
+
+Prints ONE JSON line.  Besides periods/s it reports:
+  roofline      the dominant kernel (the fused sweep), timed live with HIP
+                events on the launch stream over a sweep-only region
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same workload
+  adjoint       the adjoint/forward time ratio of the gradient at L = 24
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Floquet periods/sec + HBM GB/s at L=30 fp32; adjoint/forward time ratio"
+PEAK_HBM_GBPS = 8000.0
+PEAK_FP32_PUBLISHED = 157.3        # TFLOP/s, counts packed dual-FP32 FMAs
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (one FMA) x 2.4 GHz: the FP32 VALU
+# rate without packed FP32 instructions, which this build does not emit.
+PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--L", type=int, default=30)
+    ap.add_argument("--periods-per-step", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-sample-gates", type=int, default=3)
+    return ap.parse_args()
+
+
+def plan_passes(fl, L, n):
+    """Number of sweep launches the library runs for n periods (header word 3
+    of the flattened plan)."""
+    return int(fl.fl_plan_query(L, "c64", 0, n, False)[3])
+
+
+def cpu_baseline(L, nsample):
+    """The oracle as it stands, timed on a bounded sample: nsample gate
+    applications spread over the chain at full size L, scaled to periods/s."""
+    import numpy as np
+
+    import floquet_inputs as fin
+    import oracle as O
+    w = fin.xyz_workload(L)
+    hs = O.xyz_bond_hamiltonians(L, w["J"], w["fields"])
+    G = O.floquet_gates(hs, w["T"])
+    psi = np.full(1 << L, 1.0 / np.sqrt(float(1 << L)), dtype=np.complex128)
+    bonds = [int(round(x)) for x in np.linspace(0, L - 2, nsample)]
+    t0 = time.perf_counter()
+    for b in bonds:
+        psi = O.apply_bond(psi, L, b, G[b])
+    dt = time.perf_counter() - t0
+    s_per_gate = dt / len(bonds)
+    s_per_period = s_per_gate * (L - 1)
+    return {"value": 1.0 / s_per_period, "unit": "periods/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(bonds)} FP64 gate applications (bonds {bonds}) at L={L}, "
+                      f"{dt:.1f} s, scaled by {L - 1} gates/period; numpy einsum, single thread",
+            "s_per_period": s_per_period, "host": platform.processor() or platform.machine(),
+            "host_cpus": os.cpu_count()}
+
+
+def adjoint_ratio(fl, torch, L=24, n=200, K=50):
+    import floquet_inputs as fin
+    w = fin.xyz_workload(L)
+    eng = fl.FloquetEngine(L, "c64")
+    eng.set_xyz(w["J"], w["fields"], w["T"])
+    psi = eng.new_state()
+    gens = fl.fl_xyz_generators(L)
+    lam = torch.empty_like(psi)
+    ck = [torch.empty_like(psi) for _ in range(n // K)]
+    res = {}
+    for rep in range(2):          # first repetition warms up plans and caches
+        eng.init(psi, w["spinors"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(n // K):
+            ck[s].copy_(psi)
+            eng.step(psi, K)
+        E, _ = eng.energy(psi)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g = fl.fl_grad(eng.ctx, psi, ck, n, K, gens, lam)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"L": L, "n_periods": n, "ckpt_every": K, "forward_s": t1 - t0, "backward_s": t2 - t1,
+               "ratio_backward_over_forward": (t2 - t1) / (t1 - t0),
+               "ratio_total_over_forward": (t2 - t0) / (t1 - t0), "dE_dT": float(g[-1])}
+    return res
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import floquet_inputs as fin
+    import paper_2111_08044_amd as fl
+
+    L, m = args.L, args.periods_per_step
+    torch.cuda.set_device(0)
+    w = fin.xyz_workload(L)
+    eng = fl.FloquetEngine(L, "c64")
+    eng.set_xyz(w["J"], w["fields"], w["T"])
+    psi = eng.new_state()
+    eng.init(psi, w["spinors"])
+    e_series = []
+    for _ in range(args.warmup):
+        eng.step(psi, m)
+        e_series.append(eng.energy_density(psi))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eng.step(psi, m)
+        e_series.append(eng.energy_density(psi))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    periods = args.steps * m
+    periods_per_s = periods / wall
+
+    # ---- dominant kernel: sweep-only region timed with events on the launch stream
+    nblk = 16
+    reps = 4
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    eng.step(psi, nblk)
+    ev0.record(stream)
+    for _ in range(reps):
+        eng.step(psi, nblk)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sweep_ms = ev0.elapsed_time(ev1)
+    launches = plan_passes(fl, L, nblk) * reps
+    avg_launch_s = sweep_ms / 1e3 / launches
+    gates = (L - 1) * nblk * reps
+    flops = 32.0 * (1 << L) * gates                 # 16 FMA per amplitude per gate
+    bytes_ = 16.0 * (1 << L) * launches             # read + write of every amplitude per pass
+    achieved_tflops = flops / (sweep_ms / 1e3) / 1e12
+    achieved_gbps = bytes_ / (sweep_ms / 1e3) / 1e9
+    roof = {"kernel": "k_sweep<float,4,13>", "bound": "alu", "achieved": round(achieved_tflops, 3),
+            "peak": round(PEAK_FP32_VALU, 2), "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU, 4),
+            "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "flops_per_launch": flops / launches, "bytes_per_launch": bytes_ / launches,
+            "hbm_gbps": round(achieved_gbps, 1), "hbm_frac": round(achieved_gbps / PEAK_HBM_GBPS, 4),
+            "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4),
+            "passes_per_period": launches / (nblk * reps), "gates_per_pass": gates / launches}
+
+    out = {
+        "metric": METRIC, "value": round(periods_per_s, 3), "unit": "periods/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Floquet brickwork, L={L} XYZ+fields chain, complex64 state, plain fused sweep, "
+                               f"T=0.25, seed 2111, {m} periods + 1 energy readout per step",
+                   "L": L, "periods_per_step": m, "state_gib": (1 << L) * 8 / 2**30},
+        "gates_per_s": round(periods_per_s * (L - 1), 1),
+        "hbm_gbps_algorithmic": round(16.0 * (1 << L) * roof["passes_per_period"] * periods_per_s / 1e9, 1),
+        "energy_density_last": e_series[-1],
+        "roofline": roof,
+    }
+    del psi
+    torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_ratio(fl, torch)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(L, args.cpu_sample_gates)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,672 @@
+// C ABI of the Floquet brickwork engine (declared in include/floquet.h).
+//
+// Host responsibilities only: argument validation, FP64 gate construction,
+// pass planning (cached per context), launch sequencing on the caller's
+// stream, and the final FP64 contractions of the reduced quantities the
+// kernels return (bond energies, gradient contractions).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "floquet.h"
+#include "fl_common.h"
+#include "host_math.h"
+#include "kernels.h"
+#include "planner.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return FL_EHIP;
+}
+
+#define FL_HIP(x)                                      \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return fail_hip(e_, #x); \
+    } while (0)
+
+constexpr int kPlanBlock = 16;        // periods per planned block
+constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
+constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
+constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
+
+int kmax_of(int dtype) { return dtype == FL_C64 ? FL_KMAX_C64 : FL_KMAX_C128; }
+size_t amp_bytes(int dtype) { return dtype == FL_C64 ? 8 : 16; }
+
+}  // namespace
+
+struct fl_ctx {
+    int L = 0, dtype = 0, variant = 0, dev = 0;
+    hipStream_t stream = nullptr;
+    fl_geom geom{}, geom_adj{};
+    bool have_gates = false, have_h = false;
+    double T = 0.0;
+    std::vector<cd> h, G;  // FP64, (L-1) x 16
+    void* d_gates = nullptr;   // 2 (L-1) gates, 32 reals each, context precision
+    void* d_h = nullptr;       // (L-1) bond Hamiltonians, 32 reals each
+    double* d_part = nullptr;  // reduction partials [kReduceGrid][L][16]
+    double* d_red = nullptr;   // finalized reductions, 2 x L x 16
+    double* h_red = nullptr;   // pinned host copy
+    void* d_tabs = nullptr;    // product-state factor tables
+    double* d_mpart = nullptr; // gradient partials [kAdjGrid][L-1][16]
+    std::map<std::pair<int, int>, std::vector<fl_pass>> plans;
+    std::map<int, std::vector<fl_pass>> adj_plans;
+    std::vector<fl_pass> cover;
+};
+
+namespace {
+
+uint32_t ntiles(const fl_geom& g) { return 1u << (g.L - g.K); }
+
+const std::vector<fl_pass>& get_plan(fl_ctx* c, int n, bool dagger) {
+    auto key = std::make_pair(n, dagger ? 1 : 0);
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) return it->second;
+    auto& v = c->plans[key];
+    v = fl::plan_sweep(c->geom, n, dagger, false, kMaxGatesPerPass);
+    return v;
+}
+
+const std::vector<fl_pass>& get_adj_plan(fl_ctx* c, int n) {
+    auto it = c->adj_plans.find(n);
+    if (it != c->adj_plans.end()) return it->second;
+    auto& v = c->adj_plans[n];
+    v = fl::plan_sweep(c->geom_adj, n, true, true, kMaxGatesPerPass);
+    return v;
+}
+
+bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+int check_state(const fl_ctx* c, const void* p, const char* name) {
+    if (!p) return fail(FL_EINVAL, std::string(name) + " is NULL");
+    if (((uintptr_t)p) & 255) return fail(FL_EINVAL, std::string(name) + " is not 256-byte aligned");
+    if (!is_device_ptr(p)) return fail(FL_EINVAL, std::string(name) + " is not device memory");
+    (void)c;
+    return FL_OK;
+}
+
+bool finite_all(const double* a, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+// Round FP64 complex matrices to the context precision, 32 reals per 4x4.
+int upload_mats(fl_ctx* c, void* dst, const std::vector<cd>& m, size_t nmat) {
+    if (c->dtype == FL_C64) {
+        std::vector<float> t(nmat * 32);
+        for (size_t i = 0; i < nmat * 16; ++i) {
+            t[2 * i] = (float)m[i].real();
+            t[2 * i + 1] = (float)m[i].imag();
+        }
+        FL_HIP(hipMemcpy(dst, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+        std::vector<double> t(nmat * 32);
+        for (size_t i = 0; i < nmat * 16; ++i) {
+            t[2 * i] = m[i].real();
+            t[2 * i + 1] = m[i].imag();
+        }
+        FL_HIP(hipMemcpy(dst, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return FL_OK;
+}
+
+int install_gates(fl_ctx* c) {
+    const int nb = c->L - 1;
+    std::vector<cd> both((size_t)2 * nb * 16);
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                both[(size_t)b * 16 + 4 * i + j] = c->G[(size_t)b * 16 + 4 * i + j];
+                both[(size_t)(nb + b) * 16 + 4 * i + j] = std::conj(c->G[(size_t)b * 16 + 4 * j + i]);
+            }
+    int rc = upload_mats(c, c->d_gates, both, (size_t)2 * nb);
+    if (rc) return rc;
+    if (c->have_h) return upload_mats(c, c->d_h, c->h, nb);
+    return FL_OK;
+}
+
+void read_c16(const double* src, cd* dst) {
+    for (int i = 0; i < 16; ++i) dst[i] = cd(src[2 * i], src[2 * i + 1]);
+}
+
+// rho (4x4) from the 16 reals of a bond reduction.
+void rho_from16(const double* v, cd* rho) {
+    for (int i = 0; i < 4; ++i) rho[5 * i] = v[i];
+    int k = 4;
+    for (int i = 0; i < 4; ++i)
+        for (int j = i + 1; j < 4; ++j) {
+            rho[4 * i + j] = cd(v[k], v[k + 1]);
+            rho[4 * j + i] = cd(v[k], -v[k + 1]);
+            k += 2;
+        }
+}
+
+int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
+    const int grid = (int)std::min<uint32_t>(ntiles(c->geom), kReduceGrid);
+    for (const fl_pass& p : c->cover) {
+        hipError_t e = fl::launch_rdm(c->dtype, c->geom, psi, p, c->d_part, grid, c->L, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_rdm launch");
+    }
+    *grid_out = grid;
+    return FL_OK;
+}
+
+int run_periods(fl_ctx* c, void* psi, int64_t n, bool dagger) {
+    const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+    if (q > 0) {
+        const auto& pb = get_plan(c, kPlanBlock, dagger);
+        for (int64_t i = 0; i < q; ++i)
+            for (const fl_pass& p : pb) {
+                hipError_t e = fl::launch_sweep(c->dtype, c->geom, psi, c->d_gates, p, c->stream);
+                if (e != hipSuccess) return fail_hip(e, "k_sweep launch");
+            }
+    }
+    if (r > 0) {
+        const auto& pr = get_plan(c, (int)r, dagger);
+        for (const fl_pass& p : pr) {
+            hipError_t e = fl::launch_sweep(c->dtype, c->geom, psi, c->d_gates, p, c->stream);
+            if (e != hipSuccess) return fail_hip(e, "k_sweep launch");
+        }
+    }
+    return FL_OK;
+}
+
+int run_reverse(fl_ctx* c, void* psi, void* lam, int64_t n) {
+    const int grid = (int)std::min<uint32_t>(ntiles(c->geom_adj), kAdjGrid);
+    const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+    auto go = [&](const std::vector<fl_pass>& plan) -> int {
+        for (const fl_pass& p : plan) {
+            hipError_t e = fl::launch_adjoint(c->dtype, c->geom_adj, psi, lam, c->d_gates, p, c->d_mpart, grid,
+                                              c->stream);
+            if (e != hipSuccess) return fail_hip(e, "k_adjoint launch");
+        }
+        return FL_OK;
+    };
+    for (int64_t i = 0; i < q; ++i) {
+        int rc = go(get_adj_plan(c, kPlanBlock));
+        if (rc) return rc;
+    }
+    if (r > 0) return go(get_adj_plan(c, (int)r));
+    return FL_OK;
+}
+
+int apply_h0(fl_ctx* c, const void* psi, void* out) {
+    bool first = true;
+    for (const fl_pass& p : c->cover) {
+        hipError_t e = fl::launch_apply_h(c->dtype, c->geom, psi, out, c->d_h, p, first ? 1 : 0, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_apply_h launch");
+        first = false;
+    }
+    return FL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fl_last_error(void) { return g_err.c_str(); }
+
+int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
+    if (!ctx) return fail(FL_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "dtype must be FL_C64 or FL_C128");
+    const int lmax = dtype == FL_C64 ? 34 : 33;
+    if (L < 2 || L > lmax) return fail(FL_EINVAL, "L out of range [2, " + std::to_string(lmax) + "]");
+    if (variant != FL_PLAIN) return fail(FL_EINVAL, "variant not available in this build");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return fail(FL_ENODEV, "no HIP device");
+    }
+    int dev = 0;
+    FL_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    FL_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(FL_ENODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    fl_ctx* c = new fl_ctx();
+    c->L = L;
+    c->dtype = dtype;
+    c->variant = variant;
+    c->dev = dev;
+    c->stream = (hipStream_t)hip_stream;
+    c->geom = fl::make_geom(L, kmax_of(dtype), 4);
+    c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4);
+    c->cover = fl::plan_cover(c->geom);
+    const int nb = L - 1;
+    const size_t rb = dtype == FL_C64 ? 4 : 8;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = hipMalloc(&c->d_gates, (size_t)2 * nb * 32 * rb);
+    if (e == hipSuccess) e = hipMalloc(&c->d_h, (size_t)nb * 32 * rb);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_part, (size_t)kReduceGrid * L * 16 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_red, (size_t)2 * L * 16 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_red, (size_t)2 * L * 16 * sizeof(double), 0);
+    if (e == hipSuccess) e = hipMalloc(&c->d_tabs, (size_t)3 * 4096 * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_mpart, (size_t)kAdjGrid * nb * 16 * sizeof(double));
+    if (e != hipSuccess) {
+        fl_destroy(c);
+        (void)hipGetLastError();
+        return fail(FL_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    *ctx = c;
+    return FL_OK;
+}
+
+int fl_destroy(fl_ctx* c) {
+    if (!c) return FL_OK;
+    if (c->d_gates) (void)hipFree(c->d_gates);
+    if (c->d_h) (void)hipFree(c->d_h);
+    if (c->d_part) (void)hipFree(c->d_part);
+    if (c->d_red) (void)hipFree(c->d_red);
+    if (c->h_red) (void)hipHostFree(c->h_red);
+    if (c->d_tabs) (void)hipFree(c->d_tabs);
+    if (c->d_mpart) (void)hipFree(c->d_mpart);
+    delete c;
+    return FL_OK;
+}
+
+int fl_set_stream(fl_ctx* c, void* hip_stream) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    c->stream = (hipStream_t)hip_stream;
+    return FL_OK;
+}
+
+int fl_set_bonds(fl_ctx* c, const double* h, double T) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!h) return fail(FL_EINVAL, "h is NULL");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FL_EINVAL, "T must be finite and > 0");
+    const int nb = c->L - 1;
+    if (!finite_all(h, (size_t)nb * 32)) return fail(FL_EINVAL, "h has non-finite entries");
+    std::vector<cd> hv((size_t)nb * 16);
+    for (int b = 0; b < nb; ++b) read_c16(h + (size_t)b * 32, &hv[(size_t)b * 16]);
+    for (int b = 0; b < nb; ++b) {
+        const cd* m = &hv[(size_t)b * 16];
+        double scale = 0.0, asym = 0.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                scale = std::max(scale, std::abs(m[4 * i + j]));
+                asym = std::max(asym, std::abs(m[4 * i + j] - std::conj(m[4 * j + i])));
+            }
+        if (asym > 1e-12 * std::max(1.0, scale))
+            return fail(FL_EINVAL, "h[" + std::to_string(b) + "] is not Hermitian");
+    }
+    c->h = hv;
+    c->G.assign((size_t)nb * 16, cd(0));
+    for (int b = 0; b < nb; ++b) fl::gate_exp(&hv[(size_t)b * 16], 0.5 * T, &c->G[(size_t)b * 16]);
+    c->T = T;
+    c->have_h = true;
+    int rc = install_gates(c);
+    if (rc) return rc;
+    c->have_gates = true;
+    return FL_OK;
+}
+
+int fl_set_gates(fl_ctx* c, const double* G, const double* h, double T) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if (!G) return fail(FL_EINVAL, "G is NULL");
+    const int nb = c->L - 1;
+    if (!finite_all(G, (size_t)nb * 32) || (h && !finite_all(h, (size_t)nb * 32)))
+        return fail(FL_EINVAL, "non-finite entries");
+    c->G.assign((size_t)nb * 16, cd(0));
+    for (int b = 0; b < nb; ++b) read_c16(G + (size_t)b * 32, &c->G[(size_t)b * 16]);
+    if (h) {
+        c->h.assign((size_t)nb * 16, cd(0));
+        for (int b = 0; b < nb; ++b) read_c16(h + (size_t)b * 32, &c->h[(size_t)b * 16]);
+        c->have_h = true;
+    } else {
+        c->h.assign((size_t)nb * 16, cd(0));
+        c->have_h = true;
+    }
+    c->T = T;
+    int rc = install_gates(c);
+    if (rc) return rc;
+    c->have_gates = true;
+    return FL_OK;
+}
+
+int fl_init_state(fl_ctx* c, void* psi, const double* spinors) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (!spinors) return fail(FL_EINVAL, "spinors is NULL");
+    const int L = c->L;
+    if (!finite_all(spinors, (size_t)L * 4)) return fail(FL_EINVAL, "spinors have non-finite entries");
+    std::vector<cd> s((size_t)2 * L);
+    for (int i = 0; i < 2 * L; ++i) s[i] = cd(spinors[2 * i], spinors[2 * i + 1]);
+    const int a = std::min(L, 12), b = std::min(L - a, 12);
+    std::vector<cd> tlo, tmid, thi;
+    fl::product_tables(L, s.data(), a, b, tlo, tmid, thi);
+    std::vector<double> buf;
+    for (auto* t : {&tlo, &tmid, &thi})
+        for (const cd& z : *t) {
+            buf.push_back(z.real());
+            buf.push_back(z.imag());
+        }
+    FL_HIP(hipMemcpyAsync(c->d_tabs, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipError_t e = fl::launch_init(c->dtype, psi, L, c->d_tabs, a, b, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_init launch");
+    // the host staging buffer must outlive the asynchronous copy
+    FL_HIP(hipStreamSynchronize(c->stream));
+    return FL_OK;
+}
+
+int fl_apply_period(fl_ctx* c, void* psi, int64_t n, int dagger) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (n < 0) return fail(FL_EINVAL, "n_periods < 0");
+    if (dagger != 0 && dagger != 1) return fail(FL_EINVAL, "dagger must be 0 or 1");
+    if (!c->have_gates) return fail(FL_ESTATE, "no gates: call fl_set_bonds first");
+    return run_periods(c, psi, n, dagger == 1);
+}
+
+int fl_expect_energy(fl_ctx* c, const void* psi, double out[2], double* rdm) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (!out) return fail(FL_EINVAL, "out is NULL");
+    if (!c->have_h) return fail(FL_ESTATE, "no bond Hamiltonians: call fl_set_bonds first");
+    const int L = c->L;
+    int grid = 0;
+    rc = launch_cover_rdm(c, psi, &grid);
+    if (rc) return rc;
+    hipError_t e = fl::launch_finalize(c->d_part, grid, L * 16, c->d_red, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+    FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, (size_t)L * 16 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FL_HIP(hipStreamSynchronize(c->stream));
+    double E = 0.0;
+    for (int b = 0; b < L - 1; ++b) {
+        cd rho[16];
+        rho_from16(c->h_red + (size_t)b * 16, rho);
+        const cd* hb = &c->h[(size_t)b * 16];
+        cd tr = 0.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) tr += hb[4 * i + j] * rho[4 * j + i];
+        E += tr.real();
+        if (rdm)
+            for (int k = 0; k < 16; ++k) {
+                rdm[(size_t)b * 32 + 2 * k] = rho[k].real();
+                rdm[(size_t)b * 32 + 2 * k + 1] = rho[k].imag();
+            }
+    }
+    out[0] = E;
+    out[1] = c->h_red[(size_t)(L - 1) * 16];
+    return FL_OK;
+}
+
+int fl_overlap(fl_ctx* c, const void* phi, int dphi, const void* psi, int dpsi, double out[4]) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    if ((dphi != FL_C64 && dphi != FL_C128) || (dpsi != FL_C64 && dpsi != FL_C128))
+        return fail(FL_EINVAL, "dtype must be FL_C64 or FL_C128");
+    int rc = check_state(c, phi, "phi");
+    if (rc) return rc;
+    rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (!out) return fail(FL_EINVAL, "out is NULL");
+    const uint64_t n = 1ull << c->L;
+    const uint64_t want = (n + 255) / 256;
+    const int grid = (int)std::min<uint64_t>(want, (uint64_t)kReduceGrid);
+    hipError_t e = fl::launch_overlap(dphi, phi, dpsi, psi, n, c->d_part, grid, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_overlap launch");
+    e = fl::launch_finalize(c->d_part, grid, 4, c->d_red, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+    FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    FL_HIP(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 4; ++i) out[i] = c->h_red[i];
+    return FL_OK;
+}
+
+int fl_energy_spread(fl_ctx* c, const void* psi, void* ws, double out[3]) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    rc = check_state(c, ws, "ws");
+    if (rc) return rc;
+    if (ws == psi) return fail(FL_EINVAL, "ws must not alias psi");
+    if (!out) return fail(FL_EINVAL, "out is NULL");
+    if (!c->have_h) return fail(FL_ESTATE, "no bond Hamiltonians: call fl_set_bonds first");
+    rc = apply_h0(c, psi, ws);
+    if (rc) return rc;
+    double ov[4];
+    rc = fl_overlap(c, psi, c->dtype, ws, c->dtype, ov);
+    if (rc) return rc;
+    out[0] = ov[0];
+    out[1] = ov[3];
+    out[2] = ov[2];
+    return FL_OK;
+}
+
+int64_t fl_grad_workspace_bytes(const fl_ctx* c) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    return (int64_t)((1ull << c->L) * amp_bytes(c->dtype));
+}
+
+int fl_grad(fl_ctx* c, void* psi_n, void* const* ckpts, int64_t n, int64_t K, const double* gens, int P,
+            void* lam, double* grad) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi_n, "psi_n");
+    if (rc) return rc;
+    rc = check_state(c, lam, "lambda_ws");
+    if (rc) return rc;
+    if (lam == psi_n) return fail(FL_EINVAL, "lambda_ws must not alias psi_n");
+    if (n < 0 || K < 0) return fail(FL_EINVAL, "n_periods and K must be >= 0");
+    if (K > 0 && n % K != 0) return fail(FL_EINVAL, "n_periods must be a multiple of K");
+    if (P < 0 || (P > 0 && !gens)) return fail(FL_EINVAL, "gens is NULL or P < 0");
+    if (!grad) return fail(FL_EINVAL, "grad is NULL");
+    if (!c->have_gates || !c->have_h) return fail(FL_ESTATE, "no bonds: call fl_set_bonds first");
+    const int L = c->L, nb = L - 1;
+    const int64_t nseg = (K > 0) ? n / K : (n > 0 ? 1 : 0);
+    const int64_t seglen = (K > 0) ? K : n;
+    if (K > 0 && n > 0) {
+        if (!ckpts) return fail(FL_EINVAL, "ckpts is NULL");
+        for (int64_t s = 0; s < nseg; ++s) {
+            rc = check_state(c, ckpts[s], "ckpts[s]");
+            if (rc) return rc;
+        }
+    }
+    if (P > 0 && !finite_all(gens, (size_t)nb * P * 32)) return fail(FL_EINVAL, "gens has non-finite entries");
+    const size_t bytes = (size_t)(1ull << L) * amp_bytes(c->dtype);
+    // 1. bond density matrices of psi_n (explicit terms) -> d_red[0 .. L*16)
+    int grid = 0;
+    rc = launch_cover_rdm(c, psi_n, &grid);
+    if (rc) return rc;
+    hipError_t e = fl::launch_finalize(c->d_part, grid, L * 16, c->d_red, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+    // 2. lambda = H0 psi_n
+    rc = apply_h0(c, psi_n, lam);
+    if (rc) return rc;
+    // 3. reverse replay with checkpoint resets, accumulating D_b
+    const int agrid = (int)std::min<uint32_t>(ntiles(c->geom_adj), kAdjGrid);
+    e = fl::launch_zero(c->d_mpart, (uint64_t)agrid * nb * 16, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_zero launch");
+    for (int64_t s = nseg - 1; s >= 0; --s) {
+        rc = run_reverse(c, psi_n, lam, seglen);
+        if (rc) return rc;
+        if (K > 0) FL_HIP(hipMemcpyAsync(psi_n, ckpts[s], bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
+    e = fl::launch_finalize(c->d_mpart, agrid, nb * 16, c->d_red + (size_t)L * 16, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+    FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, (size_t)2 * L * 16 * sizeof(double), hipMemcpyDeviceToHost,
+                          c->stream));
+    FL_HIP(hipStreamSynchronize(c->stream));
+    // 4. contractions on the host (FP64):
+    //    dE/dtheta_{b,p} = Re sum_ij A_ij D_ij + tr(gen rho_b),  A = (dG/dtheta) G^dagger
+    //    dE/dT          = sum_b Re sum_ij (-(i/2) h_b)_ij D_ij
+    const double tau = 0.5 * c->T;
+    double gT = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        cd rho[16], D[16];
+        rho_from16(c->h_red + (size_t)b * 16, rho);
+        const double* v = c->h_red + (size_t)L * 16 + (size_t)b * 16;
+        for (int i = 0; i < 4; ++i) D[5 * i] = cd(0.0, 2.0 * v[i]);
+        int k = 4;
+        for (int i = 0; i < 4; ++i)
+            for (int j = i + 1; j < 4; ++j) {
+                D[4 * i + j] = cd(v[k], v[k + 1]);
+                D[4 * j + i] = -std::conj(D[4 * i + j]);
+                k += 2;
+            }
+        const cd* Gb = &c->G[(size_t)b * 16];
+        cd Gd[16];
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) Gd[4 * i + j] = std::conj(Gb[4 * j + i]);
+        for (int p = 0; p < P; ++p) {
+            cd gen[16], dG[16], A[16];
+            read_c16(gens + ((size_t)b * P + p) * 32, gen);
+            fl::gate_exp_derivative(&c->h[(size_t)b * 16], gen, tau, dG);
+            fl::mat_mul_n(dG, Gd, A, 4);
+            cd s = 0.0, ex = 0.0;
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    s += A[4 * i + j] * D[4 * i + j];
+                    ex += gen[4 * i + j] * rho[4 * j + i];
+                }
+            grad[(size_t)b * P + p] = s.real() + ex.real();
+        }
+        cd sT = 0.0;
+        for (int i = 0; i < 16; ++i) sT += cd(0.0, -0.5) * c->h[(size_t)b * 16 + i] * D[i];
+        gT += sT.real();
+    }
+    grad[(size_t)nb * P] = gT;
+    return FL_OK;
+}
+
+// ---------------------------------------------------------------- host helpers
+
+int fl_xyz_bonds(int L, const double* J, const double* fields, double* h_out) {
+    if (L < 2 || L > 64) return fail(FL_EINVAL, "L out of range");
+    if (!J || !fields || !h_out) return fail(FL_EINVAL, "NULL argument");
+    for (int b = 0; b < L - 1; ++b) {
+        cd h[16];
+        fl::xyz_bond(J + 3 * b, fields + 3 * b, fields + 3 * (b + 1), h);
+        for (int k = 0; k < 16; ++k) {
+            h_out[(size_t)b * 32 + 2 * k] = h[k].real();
+            h_out[(size_t)b * 32 + 2 * k + 1] = h[k].imag();
+        }
+    }
+    return FL_OK;
+}
+
+int fl_host_gates(int nb, const double* h, double T, double* G_out) {
+    if (nb < 1 || !h || !G_out) return fail(FL_EINVAL, "bad argument");
+    for (int b = 0; b < nb; ++b) {
+        cd hm[16], G[16];
+        read_c16(h + (size_t)b * 32, hm);
+        fl::gate_exp(hm, 0.5 * T, G);
+        for (int k = 0; k < 16; ++k) {
+            G_out[(size_t)b * 32 + 2 * k] = G[k].real();
+            G_out[(size_t)b * 32 + 2 * k + 1] = G[k].imag();
+        }
+    }
+    return FL_OK;
+}
+
+int fl_host_gate_derivative(const double* h, const double* gen, double T, double* dG_out) {
+    if (!h || !gen || !dG_out) return fail(FL_EINVAL, "NULL argument");
+    cd hm[16], gm[16], dG[16];
+    read_c16(h, hm);
+    read_c16(gen, gm);
+    fl::gate_exp_derivative(hm, gm, 0.5 * T, dG);
+    for (int k = 0; k < 16; ++k) {
+        dG_out[2 * k] = dG[k].real();
+        dG_out[2 * k + 1] = dG[k].imag();
+    }
+    return FL_OK;
+}
+
+int fl_xyz_generators(int L, double* gens_out) {
+    if (L < 2 || L > 64 || !gens_out) return fail(FL_EINVAL, "bad argument");
+    const double zero[3] = {0, 0, 0};
+    for (int b = 0; b < L - 1; ++b)
+        for (int a = 0; a < 3; ++a) {
+            double J[3] = {0, 0, 0};
+            J[a] = 1.0;
+            cd h[16];
+            fl::xyz_bond(J, zero, zero, h);
+            for (int k = 0; k < 16; ++k) {
+                gens_out[((size_t)b * 3 + a) * 32 + 2 * k] = h[k].real();
+                gens_out[((size_t)b * 3 + a) * 32 + 2 * k + 1] = h[k].imag();
+            }
+        }
+    return FL_OK;
+}
+
+int fl_tile_map(int L, int dtype, int h, uint64_t* out) {
+    if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "bad dtype");
+    if (L < 2 || L > 24 || !out) return fail(FL_EINVAL, "bad argument");
+    const fl_geom g = fl::make_geom(L, kmax_of(dtype), 4);
+    if (g.W > 0 && (h < g.C || h + g.W > L)) return fail(FL_EINVAL, "window out of range");
+    if (g.W == 0) h = g.C;
+    const uint64_t nt = 1ull << (L - g.K);
+    for (uint64_t t = 0; t < nt; ++t) {
+        const uint64_t base = fl_tile_base(t, g.C, g.W, h);
+        for (uint32_t j = 0; j < (1u << g.K); ++j) out[(t << g.K) + j] = base + fl_tile_offset(j, g.C, h);
+    }
+    return FL_OK;
+}
+
+int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* buf, int64_t cap, int64_t* needed) {
+    if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "bad dtype");
+    if (L < 2 || L > (dtype == FL_C64 ? 34 : 33)) return fail(FL_EINVAL, "L out of range");
+    if (n < 0 || n > 100000) return fail(FL_EINVAL, "n out of range for a query");
+    if (!needed) return fail(FL_EINVAL, "needed is NULL");
+    std::vector<fl_pass> plan;
+    fl_geom g;
+    if (kind == 0) {
+        g = fl::make_geom(L, kmax_of(dtype), 4);
+        const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+        std::vector<fl_pass> pb, pr;
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass);
+        for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
+        plan.insert(plan.end(), pr.begin(), pr.end());
+    } else if (kind == 1) {
+        g = fl::make_geom(L, FL_KMAX_ADJ, 4);
+        const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+        std::vector<fl_pass> pb, pr;
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, true, true, kMaxGatesPerPass);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, true, true, kMaxGatesPerPass);
+        for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
+        plan.insert(plan.end(), pr.begin(), pr.end());
+    } else if (kind == 2) {
+        g = fl::make_geom(L, kmax_of(dtype), 4);
+        plan = fl::plan_cover(g);
+    } else {
+        return fail(FL_EINVAL, "kind must be 0, 1 or 2");
+    }
+    std::vector<int> words;
+    fl::serialize_plan(g, plan, words);
+    *needed = (int64_t)words.size();
+    if (buf) {
+        const int64_t m = std::min<int64_t>(cap, (int64_t)words.size());
+        for (int64_t i = 0; i < m; ++i) buf[i] = words[i];
+    }
+    return FL_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,207 @@
+// Host-side FP64 mathematics of the engine: bond Hamiltonians of the
+// XYZ-plus-fields chain, gate exponentials G_b = exp(-i (T/2) h_b) (Sec. III A,
+// Eq. (5)), their parameter derivatives for the reverse-mode gradient, dense
+// fused window matrices, and the product-state factor tables.
+//
+// The exponential of a 4x4 Hermitian h is taken through its eigendecomposition
+// h = V diag(lambda) V^dagger, computed with the cyclic complex Jacobi method
+// (Jacobi 1846; e.g. Golub & Van Loan, "Matrix Computations", Sec. 8.5):
+// exp(-i tau h) = V diag(exp(-i tau lambda)) V^dagger.  Derivatives use the
+// Daleckii-Krein formula: for f = exp and X = -i tau h = V diag(x) V^dagger,
+//   Df(X)[E] = V (Gamma o (V^dagger E V)) V^dagger,
+//   Gamma_kl = (e^{x_k} - e^{x_l}) / (x_k - x_l)
+//            = e^{-i tau (l_k + l_l)/2} sinc(tau (l_k - l_l)/2),
+// which stays exact for (near-)degenerate eigenvalues.
+#include "host_math.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace fl {
+
+using cd = std::complex<double>;
+
+static void mat4_mul(const cd* A, const cd* B, cd* C) {
+    cd t[16];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            cd s = 0;
+            for (int k = 0; k < 4; ++k) s += A[4 * i + k] * B[4 * k + j];
+            t[4 * i + j] = s;
+        }
+    std::memcpy(C, t, sizeof(t));
+}
+
+static void mat4_adj(const cd* A, cd* B) {
+    cd t[16];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) t[4 * i + j] = std::conj(A[4 * j + i]);
+    std::memcpy(B, t, sizeof(t));
+}
+
+void herm_eig4(const cd* h, double* lam, cd* V) {
+    cd A[16];
+    for (int i = 0; i < 16; ++i) A[i] = h[i];
+    // symmetrise: A = (h + h^dagger)/2 so that rounding in the input cannot
+    // leave a non-Hermitian residue
+    for (int i = 0; i < 4; ++i)
+        for (int j = i; j < 4; ++j) {
+            cd s = 0.5 * (A[4 * i + j] + std::conj(A[4 * j + i]));
+            A[4 * i + j] = s;
+            A[4 * j + i] = std::conj(s);
+        }
+    for (int i = 0; i < 16; ++i) V[i] = (i % 5 == 0) ? cd(1.0) : cd(0.0);
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                double a = std::norm(A[4 * i + j]);
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-34 * tot || off == 0.0) break;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const cd apq = A[4 * p + q];
+                const double r = std::abs(apq);
+                if (r == 0.0) continue;
+                // phase that makes the (p,q) entry real and positive
+                const cd ph = apq / r;
+                const double app = A[4 * p + p].real(), aqq = A[4 * q + q].real();
+                // real Jacobi rotation zeroing the real symmetric 2x2 block
+                const double zeta = (aqq - app) / (2.0 * r);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t);
+                const double s = t * c;
+                // U = D R with D = diag(1,..,conj(ph) at q,..), R the rotation
+                // U[p][p] = c, U[p][q] = s, U[q][p] = -s conj(ph), U[q][q] = c conj(ph)
+                cd U[16];
+                for (int i = 0; i < 16; ++i) U[i] = (i % 5 == 0) ? cd(1.0) : cd(0.0);
+                U[4 * p + p] = c;
+                U[4 * p + q] = s;
+                U[4 * q + p] = -s * std::conj(ph);
+                U[4 * q + q] = c * std::conj(ph);
+                cd Ud[16];
+                mat4_adj(U, Ud);
+                mat4_mul(Ud, A, A);
+                mat4_mul(A, U, A);
+                mat4_mul(V, U, V);
+                A[4 * p + q] = 0.0;
+                A[4 * q + p] = 0.0;
+            }
+    }
+    for (int i = 0; i < 4; ++i) lam[i] = A[4 * i + i].real();
+}
+
+void gate_exp(const cd* h, double tau, cd* G) {
+    double lam[4];
+    cd V[16];
+    herm_eig4(h, lam, V);
+    cd D[16];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) D[4 * i + j] = V[4 * i + j] * std::polar(1.0, -tau * lam[j]);
+    cd Vd[16];
+    mat4_adj(V, Vd);
+    mat4_mul(D, Vd, G);
+    // one Newton-Schulz step towards the unitary polar factor:
+    // G <- G (3 I - G^dagger G) / 2 (removes the O(eps) non-unitarity)
+    cd Gd[16], GG[16];
+    mat4_adj(G, Gd);
+    mat4_mul(Gd, G, GG);
+    for (int i = 0; i < 16; ++i) GG[i] = ((i % 5 == 0) ? cd(3.0) : cd(0.0)) - GG[i];
+    mat4_mul(G, GG, G);
+    for (int i = 0; i < 16; ++i) G[i] *= 0.5;
+}
+
+static cd sinc_phase(double tau, double lk, double ll) {
+    const double y = 0.5 * tau * (lk - ll);
+    const double sc = (std::fabs(y) < 1e-8) ? 1.0 - y * y / 6.0 : std::sin(y) / y;
+    return std::polar(sc, -0.5 * tau * (lk + ll));
+}
+
+void gate_exp_derivative(const cd* h, const cd* gen, double tau, cd* dG) {
+    double lam[4];
+    cd V[16];
+    herm_eig4(h, lam, V);
+    cd Vd[16], E[16], T[16];
+    mat4_adj(V, Vd);
+    // E = V^dagger (-i tau gen) V
+    for (int i = 0; i < 16; ++i) T[i] = cd(0.0, -tau) * gen[i];
+    mat4_mul(Vd, T, E);
+    mat4_mul(E, V, E);
+    for (int k = 0; k < 4; ++k)
+        for (int l = 0; l < 4; ++l) E[4 * k + l] *= sinc_phase(tau, lam[k], lam[l]);
+    mat4_mul(V, E, E);
+    mat4_mul(E, Vd, dG);
+}
+
+void xyz_bond(const double* J3, const double* fl3, const double* fr3, cd* h) {
+    // Pauli matrices, local index 2*bit_left + bit_right; left factor acts on
+    // the lower site of the bond.
+    const cd X[4] = {0, 1, 1, 0};
+    const cd Y[4] = {0, cd(0, -1), cd(0, 1), 0};
+    const cd Z[4] = {1, 0, 0, -1};
+    const cd I[4] = {1, 0, 0, 1};
+    const cd* P[3] = {X, Y, Z};
+    for (int i = 0; i < 16; ++i) h[i] = 0.0;
+    auto kron_add = [&](const cd* A, const cd* B, cd w) {
+        for (int a0 = 0; a0 < 2; ++a0)
+            for (int b0 = 0; b0 < 2; ++b0)
+                for (int a1 = 0; a1 < 2; ++a1)
+                    for (int b1 = 0; b1 < 2; ++b1)
+                        h[4 * (2 * a0 + b0) + (2 * a1 + b1)] += w * A[2 * a0 + a1] * B[2 * b0 + b1];
+    };
+    for (int a = 0; a < 3; ++a) {
+        kron_add(P[a], P[a], J3[a]);
+        kron_add(P[a], I, 0.5 * fl3[a]);
+        kron_add(I, P[a], 0.5 * fr3[a]);
+    }
+}
+
+void mat_mul_n(const cd* A, const cd* B, cd* C, int n) {
+    std::vector<cd> t((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cd s = 0;
+            for (int k = 0; k < n; ++k) s += A[(size_t)i * n + k] * B[(size_t)k * n + j];
+            t[(size_t)i * n + j] = s;
+        }
+    std::memcpy(C, t.data(), sizeof(cd) * n * n);
+}
+
+void embed_gate(const cd* G, int nbits, int i, cd* U) {
+    // U = I (x) G (x) I acting on window bits (i, i+1) of an nbits-bit window;
+    // window index w, local gate index 2*bit(i+1) + bit(i).
+    const int n = 1 << nbits;
+    for (int r = 0; r < n * n; ++r) U[r] = 0.0;
+    for (int w = 0; w < n; ++w) {
+        const int rest = w & ~(3 << i);
+        const int col_l = (w >> i) & 3;
+        for (int row_l = 0; row_l < 4; ++row_l) {
+            const int wr = rest | (row_l << i);
+            U[(size_t)wr * n + w] += G[4 * row_l + col_l];
+        }
+    }
+}
+
+void product_tables(int L, const cd* spinors, int a, int b, std::vector<cd>& tlo,
+                    std::vector<cd>& tmid, std::vector<cd>& thi) {
+    // x = (xhi << (a+b)) | (xmid << a) | xlo; bit q of x belongs to site L-1-q.
+    auto build = [&](int first_bit, int nbits, std::vector<cd>& t) {
+        t.assign((size_t)1 << nbits, cd(1.0));
+        for (int v = 0; v < (1 << nbits); ++v) {
+            cd p = 1.0;
+            for (int k = 0; k < nbits; ++k) {
+                const int q = first_bit + k;
+                const int site = L - 1 - q;
+                p *= spinors[2 * site + ((v >> k) & 1)];
+            }
+            t[v] = p;
+        }
+    };
+    build(0, a, tlo);
+    build(a, b, tmid);
+    build(a + b, L - a - b, thi);
+}
+
+}  // namespace fl

@@ -1,0 +1,33 @@
+// Host-side FP64 mathematics (see host_math.cpp).
+#pragma once
+#include <complex>
+#include <vector>
+
+namespace fl {
+
+// Eigendecomposition of a 4x4 Hermitian matrix (row-major): h = V diag(lam) V^dagger.
+void herm_eig4(const std::complex<double>* h, double* lam, std::complex<double>* V);
+
+// G = exp(-i tau h) for a 4x4 Hermitian h.
+void gate_exp(const std::complex<double>* h, double tau, std::complex<double>* G);
+
+// d/dtheta exp(-i tau h(theta)) in the direction dh/dtheta = gen.
+void gate_exp_derivative(const std::complex<double>* h, const std::complex<double>* gen,
+                         double tau, std::complex<double>* dG);
+
+// Bond Hamiltonian Jx XX + Jy YY + Jz ZZ + (1/2) fl.sigma (x) I + (1/2) I (x) fr.sigma.
+void xyz_bond(const double* J3, const double* fl3, const double* fr3, std::complex<double>* h);
+
+// C = A B for n x n row-major complex matrices (C may alias A or B).
+void mat_mul_n(const std::complex<double>* A, const std::complex<double>* B,
+               std::complex<double>* C, int n);
+
+// Embed a 4x4 gate on bits (i, i+1) of an nbits-bit window into a 2^nbits matrix.
+void embed_gate(const std::complex<double>* G, int nbits, int i, std::complex<double>* U);
+
+// Factor tables of a product state psi[x] = thi[x >> (a+b)] tmid[(x >> a) & (2^b-1)] tlo[x & (2^a-1)].
+void product_tables(int L, const std::complex<double>* spinors, int a, int b,
+                    std::vector<std::complex<double>>& tlo, std::vector<std::complex<double>>& tmid,
+                    std::vector<std::complex<double>>& thi);
+
+}  // namespace fl

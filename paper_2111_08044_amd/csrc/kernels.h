@@ -1,0 +1,23 @@
+// Launch wrappers of the HIP kernels (kernels.hip).  dtype: 0 = complex64,
+// 1 = complex128.  All launches are asynchronous on stream s.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fl_common.h"
+
+namespace fl {
+
+hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gates, const fl_pass& pd, hipStream_t s);
+hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
+                      int nslot, hipStream_t s);
+hipError_t launch_finalize(const double* partials, int nblocks, int nvals, double* out, hipStream_t s);
+hipError_t launch_init(int dtype, void* psi, int L, const void* tabs, int a, int b, hipStream_t s);
+hipError_t launch_overlap(int dta, const void* a, int dtb, const void* b, uint64_t n, double* partials, int grid,
+                          hipStream_t s);
+hipError_t launch_apply_h(int dtype, const fl_geom& g, const void* psi, void* lam, const void* hmat, const fl_pass& pd,
+                          int first, hipStream_t s);
+hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, const void* gates, const fl_pass& pd,
+                          double* Mpart, int grid, hipStream_t s);
+hipError_t launch_zero(double* p, uint64_t n, hipStream_t s);
+
+}  // namespace fl

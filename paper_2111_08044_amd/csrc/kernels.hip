@@ -1,0 +1,727 @@
+// HIP kernels of the Floquet brickwork engine (gfx950, wave64).
+//
+//  k_sweep    fused gate sweep: one HBM read + write of the state applies
+//             every gate of a pass (Sec. II Eq. (2), fused as in Sec. II).
+//  k_rdm      two-site reduced density matrices of every bond in a pass plus
+//             the norm, FP64 accumulation (Sec. II Eq. (1); Sec. IV Eq. (10)).
+//  k_init     product initial state (Sec. IV Eq. (9) form; product of spinors).
+//  k_overlap  <phi|psi> and both norms across precisions (Sec. V echo measure).
+//  k_finalize deterministic sum of per-workgroup partials.
+//
+// Tile kernels stage a tile of 2^K amplitudes in LDS (see fl_common.h for
+// the geometry), then each thread loads 2^R amplitudes of one register group
+// into VGPRs, applies the group's 4x4 gates there and writes them back.
+#include <hip/hip_runtime.h>
+
+#include "fl_common.h"
+#include "kernels.h"
+
+namespace fl {
+
+template <typename T> struct CT;
+template <> struct CT<float> { typedef float2 c; };
+template <> struct CT<double> { typedef double2 c; };
+
+// ---------------------------------------------------------------------------
+// register-level gate application
+// ---------------------------------------------------------------------------
+
+// out_i = sum_j G_ij a_j on the four amplitudes whose register index has bits
+// (I, I+1) = local index (2*bit(I+1) + bit(I)), for every value of the other
+// R-2 register bits.  G holds 16 complex entries, row-major, (re, im) pairs.
+template <typename T, int R, int I>
+__device__ __forceinline__ void apply_pair(T (&vr)[1 << R], T (&vi)[1 << R], const T* __restrict__ G) {
+    T g[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) g[k] = G[k];
+#pragma unroll
+    for (int c = 0; c < (1 << (R - 2)); ++c) {
+        const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+        T ar[4], ai[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            ar[l] = vr[b | (l << I)];
+            ai[l] = vi[b | (l << I)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T sr = g[8 * i] * ar[0];
+            T si = g[8 * i] * ai[0];
+            sr = fma(-g[8 * i + 1], ai[0], sr);
+            si = fma(g[8 * i + 1], ar[0], si);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                sr = fma(g[8 * i + 2 * j], ar[j], sr);
+                sr = fma(-g[8 * i + 2 * j + 1], ai[j], sr);
+                si = fma(g[8 * i + 2 * j], ai[j], si);
+                si = fma(g[8 * i + 2 * j + 1], ar[j], si);
+            }
+            vr[b | (i << I)] = sr;
+            vi[b | (i << I)] = si;
+        }
+    }
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void apply_op(T (&vr)[1 << R], T (&vi)[1 << R], int i, const T* __restrict__ G) {
+    if constexpr (R >= 2) if (i == 0) { apply_pair<T, R, 0>(vr, vi, G); return; }
+    if constexpr (R >= 3) if (i == 1) { apply_pair<T, R, 1>(vr, vi, G); return; }
+    if constexpr (R >= 4) if (i == 2) { apply_pair<T, R, 2>(vr, vi, G); return; }
+    if constexpr (R >= 5) if (i == 3) { apply_pair<T, R, 3>(vr, vi, G); return; }
+}
+
+// ---------------------------------------------------------------------------
+// tile load / store (global <-> LDS), 16-byte global accesses
+// ---------------------------------------------------------------------------
+
+template <typename T, int KT>
+__device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C,
+                                          int h, typename CT<T>::c* lds) {
+    typedef typename CT<T>::c cplx;
+    if constexpr (sizeof(T) == 4) {
+        const int n2 = 1 << (K - 1);  // pairs of amplitudes
+        if constexpr (KT > 0) {
+            constexpr int ITER = (1 << (KT - 1)) / FL_NT;
+            float4 v[ITER];
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) {
+                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                v[s] = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
+            }
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) {
+                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                lds[fl_swz(j)] = make_float2(v[s].x, v[s].y);
+                lds[fl_swz(j + 1)] = make_float2(v[s].z, v[s].w);
+            }
+        } else {
+            for (int p = threadIdx.x; p < n2; p += FL_NT) {
+                const uint32_t j = 2u * p;
+                const float4 v = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
+                lds[fl_swz(j)] = make_float2(v.x, v.y);
+                lds[fl_swz(j + 1)] = make_float2(v.z, v.w);
+            }
+        }
+    } else {
+        const int n = 1 << K;
+        if constexpr (KT > 0) {
+            constexpr int ITER = (1 << KT) / FL_NT;
+            cplx v[ITER];
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) {
+                const uint32_t j = threadIdx.x + s * FL_NT;
+                v[s] = psi[base + fl_tile_offset(j, C, h)];
+            }
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) lds[fl_swz(threadIdx.x + s * FL_NT)] = v[s];
+        } else {
+            for (int j = threadIdx.x; j < n; j += FL_NT) lds[fl_swz(j)] = psi[base + fl_tile_offset(j, C, h)];
+        }
+    }
+}
+
+template <typename T, int KT>
+__device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C, int h,
+                                           const typename CT<T>::c* lds) {
+    if constexpr (sizeof(T) == 4) {
+        const int n2 = 1 << (K - 1);
+        if constexpr (KT > 0) {
+            constexpr int ITER = (1 << (KT - 1)) / FL_NT;
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) {
+                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
+                *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
+            }
+        } else {
+            for (int p = threadIdx.x; p < n2; p += FL_NT) {
+                const uint32_t j = 2u * p;
+                const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
+                *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
+            }
+        }
+    } else {
+        const int n = 1 << K;
+        for (int j = threadIdx.x; j < n; j += FL_NT) psi[base + fl_tile_offset(j, C, h)] = lds[fl_swz(j)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fused sweep
+// ---------------------------------------------------------------------------
+
+template <typename T, int R, int KT, int KMAX>
+__global__ __launch_bounds__(FL_NT) void k_sweep(typename CT<T>::c* __restrict__ psi, const T* __restrict__ gates,
+                                                 int C, int W, fl_pass pd) {
+    typedef typename CT<T>::c cplx;
+    __shared__ cplx lds[1 << KMAX];
+    const int K = KT > 0 ? KT : C + W;
+    const int h = pd.h;
+    const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
+    tile_load<T, KT>(psi, base, K, C, h, lds);
+    __syncthreads();
+    const uint32_t nsub = 1u << (K - R);
+    for (int g = 0; g < pd.ngroups; ++g) {
+        const int u0 = pd.u0[g];
+        const int nops = pd.nops[g];
+        for (uint32_t o = threadIdx.x; o < nsub; o += FL_NT) {
+            const uint32_t b0 = fl_spread(o, u0, R);
+            T vr[1 << R], vi[1 << R];
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                const cplx a = lds[fl_swz(b0 | ((uint32_t)m << u0))];
+                vr[m] = a.x;
+                vi[m] = a.y;
+            }
+            for (int q = 0; q < nops; ++q) {
+                const int gi = pd.opg[g][q];
+                if (gi >= 0) apply_op<T, R>(vr, vi, pd.opi[g][q], gates + 32 * gi);
+            }
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                cplx a;
+                a.x = vr[m];
+                a.y = vi[m];
+                lds[fl_swz(b0 | ((uint32_t)m << u0))] = a;
+            }
+        }
+        __syncthreads();
+    }
+    tile_store<T, KT>(psi, base, K, C, h, lds);
+}
+
+// ---------------------------------------------------------------------------
+// wave-level reductions
+// ---------------------------------------------------------------------------
+
+// NV values per lane -> lane l returns the wave-wide sum of value index
+// l >> (6 - log2 NV).  Each step keeps one half of the values and trades the
+// other half with the partner lane, so the whole reduction costs
+// NV/2 + NV/4 + ... shuffles instead of NV * 6.
+template <typename T, int NV>
+__device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
+    const int lane = threadIdx.x & 63;
+    constexpr int LG = (NV >= 64) ? 6 : (NV >= 32) ? 5 : (NV >= 16) ? 4 : (NV >= 8) ? 3 : (NV >= 4) ? 2 : (NV >= 2) ? 1 : 0;
+#pragma unroll
+    for (int s = 0; s < LG; ++s) {
+        const int d = 32 >> s;
+        const int half = NV >> (s + 1);
+        const bool upper = (lane & d) != 0;
+#pragma unroll
+        for (int k = 0; k < half; ++k) {
+            const T keep = upper ? v[k + half] : v[k];
+            const T send = upper ? v[k] : v[k + half];
+            v[k] = keep + __shfl_xor(send, d);
+        }
+    }
+    T r = v[0];
+#pragma unroll
+    for (int d = (32 >> LG); d >= 1; d >>= 1) r += __shfl_xor(r, d);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// reduced density matrices of the bonds of a cover pass (+ norm)
+// ---------------------------------------------------------------------------
+// Per bond: rho[i][j] = sum_r psi_{r,i} conj(psi_{r,j}); stored as 16 reals:
+// [0..3] = rho_ii, then (re, im) of rho_01, rho_02, rho_03, rho_12, rho_13, rho_23.
+// partials layout: [gridDim.x][nslot][16] doubles, slot = bond, slot L-1 = norm.
+
+#define FL_RDM_MAXG 16
+
+template <typename T, int KT, int KMAX>
+__global__ __launch_bounds__(FL_NT) void k_rdm(const typename CT<T>::c* __restrict__ psi, int C, int W,
+                                               uint32_t ntiles, fl_pass pd, double* __restrict__ partials,
+                                               int nslot) {
+    typedef typename CT<T>::c cplx;
+    __shared__ cplx lds[1 << KMAX];
+    __shared__ double wacc[FL_NT / 64][FL_RDM_MAXG + 1][16];
+    const int K = KT > 0 ? KT : C + W;
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double acc[FL_RDM_MAXG];
+#pragma unroll
+    for (int g = 0; g < FL_RDM_MAXG; ++g) acc[g] = 0.0;
+    double nrm = 0.0;
+    const uint32_t ngrp = 1u << (K - 2);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = fl_tile_base(tile, C, W, h);
+        __syncthreads();
+        tile_load<T, KT>(psi, base, K, C, h, lds);
+        __syncthreads();
+        if (pd.flags & 1) {
+            for (uint32_t j = threadIdx.x; j < (1u << K); j += FL_NT) {
+                const cplx a = lds[fl_swz(j)];
+                nrm += (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < FL_RDM_MAXG; ++g) {
+            if (g < pd.ngroups) {
+                const int u = pd.u0[g];
+                double r[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) r[k] = 0.0;
+                for (uint32_t o = threadIdx.x; o < ngrp; o += FL_NT) {
+                    const uint32_t b0 = fl_spread(o, u, 2);
+                    double ar[4], ai[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const cplx a = lds[fl_swz(b0 | ((uint32_t)l << u))];
+                        ar[l] = a.x;
+                        ai[l] = a.y;
+                    }
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) r[l] = fma(ar[l], ar[l], fma(ai[l], ai[l], r[l]));
+                    int k = 4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = i + 1; j < 4; ++j) {
+                            r[k] = fma(ar[i], ar[j], fma(ai[i], ai[j], r[k]));
+                            r[k + 1] = fma(ai[i], ar[j], fma(-ar[i], ai[j], r[k + 1]));
+                            k += 2;
+                        }
+                }
+                acc[g] += wave_transpose_reduce<double, 16>(r);
+            }
+        }
+    }
+    // per-wave accumulators -> LDS -> one row of partials per workgroup
+    double nv[1] = {nrm};
+    const double ntot = wave_transpose_reduce<double, 1>(nv);
+    if ((lane & 3) == 0) {
+#pragma unroll
+        for (int g = 0; g < FL_RDM_MAXG; ++g) wacc[wave][g][lane >> 2] = acc[g];
+    }
+    if (lane == 0) wacc[wave][FL_RDM_MAXG][0] = ntot;
+    __syncthreads();
+    for (int t = threadIdx.x; t < (pd.ngroups + 1) * 16; t += FL_NT) {
+        const int g = t >> 4, v = t & 15;
+        const int gg = (g < pd.ngroups) ? g : FL_RDM_MAXG;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < FL_NT / 64; ++w) s += wacc[w][gg][v];
+        if (g < pd.ngroups) {
+            partials[((size_t)blockIdx.x * nslot + pd.ops[g][0]) * 16 + v] = s;
+        } else if ((pd.flags & 1) && v == 0) {
+            partials[((size_t)blockIdx.x * nslot + (nslot - 1)) * 16] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// product state, overlap, finalize
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ psi, const double2* __restrict__ tlo,
+                                              const double2* __restrict__ tmid, const double2* __restrict__ thi,
+                                              int a, int b, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        const double2 p = thi[x >> (a + b)], q = tmid[(x >> a) & ((1ull << b) - 1ull)], r = tlo[x & ((1ull << a) - 1ull)];
+        const double pr = p.x * q.x - p.y * q.y, pi = p.x * q.y + p.y * q.x;
+        typename CT<T>::c o;
+        o.x = (T)(pr * r.x - pi * r.y);
+        o.y = (T)(pr * r.y + pi * r.x);
+        psi[x] = o;
+    }
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_overlap(const typename CT<TA>::c* __restrict__ a,
+                                                 const typename CT<TB>::c* __restrict__ b, uint64_t n,
+                                                 double* __restrict__ partials) {
+    __shared__ double wacc[4][4];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride) {
+        const double ar = a[x].x, ai = a[x].y, br = b[x].x, bi = b[x].y;
+        v[0] = fma(ar, br, fma(ai, bi, v[0]));     // Re conj(a) b
+        v[1] = fma(ar, bi, fma(-ai, br, v[1]));    // Im conj(a) b
+        v[2] = fma(ar, ar, fma(ai, ai, v[2]));
+        v[3] = fma(br, br, fma(bi, bi, v[3]));
+    }
+    const double r = wave_transpose_reduce<double, 4>(v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if ((lane & 15) == 0) wacc[wave][lane >> 4] = r;
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double s = 0.0;
+        for (int w = 0; w < 4; ++w) s += wacc[w][threadIdx.x];
+        partials[(size_t)blockIdx.x * 4 + threadIdx.x] = s;
+    }
+}
+
+__global__ void k_finalize(const double* __restrict__ partials, int nblocks, int nvals, double* __restrict__ out) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvals) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * nvals + v];
+    out[v] = s;
+}
+
+// ---------------------------------------------------------------------------
+// lambda = H0 psi, out of place (the Hamiltonian application of Sec. V)
+// ---------------------------------------------------------------------------
+// One cover pass per launch; the first pass writes lambda, later passes add.
+
+template <typename T, int KT, int KMAX>
+__global__ __launch_bounds__(FL_NT) void k_apply_h(const typename CT<T>::c* __restrict__ psi,
+                                                   typename CT<T>::c* __restrict__ lam, const T* __restrict__ hmat,
+                                                   int C, int W, fl_pass pd, int first) {
+    typedef typename CT<T>::c cplx;
+    __shared__ cplx lp[1 << KMAX];
+    __shared__ cplx ll[1 << KMAX];
+    const int K = KT > 0 ? KT : C + W;
+    const int h = pd.h;
+    const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
+    tile_load<T, KT>(psi, base, K, C, h, lp);
+    if (first) {
+        for (uint32_t j = threadIdx.x; j < (1u << K); j += FL_NT) {
+            cplx z;
+            z.x = 0;
+            z.y = 0;
+            ll[j] = z;
+        }
+    } else {
+        tile_load<T, KT>(lam, base, K, C, h, ll);
+    }
+    __syncthreads();
+    const uint32_t ngrp = 1u << (K - 2);
+    for (int g = 0; g < pd.ngroups; ++g) {
+        const int u = pd.u0[g];
+        const T* H = hmat + 32 * pd.ops[g][0];
+        for (uint32_t o = threadIdx.x; o < ngrp; o += FL_NT) {
+            const uint32_t b0 = fl_spread(o, u, 2);
+            T ar[4], ai[4];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const cplx a = lp[fl_swz(b0 | ((uint32_t)l << u))];
+                ar[l] = a.x;
+                ai[l] = a.y;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint32_t idx = fl_swz(b0 | ((uint32_t)i << u));
+                cplx acc = ll[idx];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const T hr = H[8 * i + 2 * j], hi = H[8 * i + 2 * j + 1];
+                    acc.x = fma(hr, ar[j], fma(-hi, ai[j], acc.x));
+                    acc.y = fma(hr, ai[j], fma(hi, ar[j], acc.y));
+                }
+                ll[idx] = acc;
+            }
+        }
+        __syncthreads();
+    }
+    tile_store<T, KT>(lam, base, K, C, h, ll);
+}
+
+// ---------------------------------------------------------------------------
+// reverse pass of the gradient: undo gates on psi and lambda together
+// ---------------------------------------------------------------------------
+// Every op with a slot first accumulates, for its bond b on register bits
+// (i, i+1), the anti-Hermitian overlap
+//   D_b[i][j] += sum_r conj(lambda_{r,i}) psi_{r,j} - conj(psi_{r,i}) lambda_{r,j}
+// (the only part of M_b = sum_r conj(lambda_{r,i}) psi_{r,j} that an
+// anti-Hermitian gate derivative A = (dG) G^dagger sees), then applies the
+// gate (G_b^dagger) to both states.  16 reals per bond:
+// [0..3] = Im(conj(lambda_i) psi_i) summed, then (re, im) of D_01, D_02,
+// D_03, D_12, D_13, D_23.
+// Mpart layout: [gridDim.x][nbonds][16] doubles, accumulated across launches.
+
+template <typename T, int R>
+__device__ __forceinline__ void adj_overlap(const T (&pr)[1 << R], const T (&pi)[1 << R], const T (&lr)[1 << R],
+                                            const T (&li)[1 << R], int i, T (&d)[16]) {
+#pragma unroll
+    for (int I = 0; I <= R - 2; ++I) {
+        if (I != i) continue;
+#pragma unroll
+        for (int c = 0; c < (1 << (R - 2)); ++c) {
+            const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+            T ar[4], ai[4], br[4], bi[4];   // a = lambda, b = psi
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                ar[l] = lr[b | (l << I)];
+                ai[l] = li[b | (l << I)];
+                br[l] = pr[b | (l << I)];
+                bi[l] = pi[b | (l << I)];
+            }
+#pragma unroll
+            for (int l = 0; l < 4; ++l) d[l] = fma(ar[l], bi[l], fma(-ai[l], br[l], d[l]));
+            int k = 4;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = x + 1; y < 4; ++y) {
+                    T re = d[k], im = d[k + 1];
+                    re = fma(ar[x], br[y], re);
+                    re = fma(ai[x], bi[y], re);
+                    re = fma(-br[x], ar[y], re);
+                    re = fma(-bi[x], ai[y], re);
+                    im = fma(ar[x], bi[y], im);
+                    im = fma(-ai[x], br[y], im);
+                    im = fma(-br[x], ai[y], im);
+                    im = fma(bi[x], ar[y], im);
+                    d[k] = re;
+                    d[k + 1] = im;
+                    k += 2;
+                }
+        }
+    }
+}
+
+template <typename T, int R, int KT, int KMAX>
+__global__ __launch_bounds__(FL_NT) void k_adjoint(typename CT<T>::c* __restrict__ psi,
+                                                   typename CT<T>::c* __restrict__ lam, const T* __restrict__ gates,
+                                                   int C, int W, uint32_t ntiles, fl_pass pd,
+                                                   double* __restrict__ Mpart, int nbonds) {
+    typedef typename CT<T>::c cplx;
+    __shared__ cplx lp[1 << KMAX];
+    __shared__ cplx ll[1 << KMAX];
+    __shared__ double wacc[FL_NT / 64][FL_MAX_SLOTS][16];
+    const int K = KT > 0 ? KT : C + W;
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t < (FL_NT / 64) * FL_MAX_SLOTS * 16; t += FL_NT) (&wacc[0][0][0])[t] = 0.0;
+    const uint32_t nsub = 1u << (K - R);   // <= FL_NT for K <= 12, R = 4
+    const bool active = threadIdx.x < nsub;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t base = fl_tile_base(tile, C, W, h);
+        __syncthreads();
+        tile_load<T, KT>(psi, base, K, C, h, lp);
+        tile_load<T, KT>(lam, base, K, C, h, ll);
+        __syncthreads();
+        for (int g = 0; g < pd.ngroups; ++g) {
+            const int u0 = pd.u0[g];
+            const int nops = pd.nops[g];
+            const uint32_t b0 = fl_spread(active ? threadIdx.x : 0u, u0, R);
+            T pr[1 << R], pi[1 << R], lr[1 << R], li[1 << R];
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                const uint32_t idx = fl_swz(b0 | ((uint32_t)m << u0));
+                cplx a = lp[idx], b = ll[idx];
+                if (!active) { a.x = a.y = b.x = b.y = 0; }
+                pr[m] = a.x;
+                pi[m] = a.y;
+                lr[m] = b.x;
+                li[m] = b.y;
+            }
+            for (int q = 0; q < nops; ++q) {
+                const int i = pd.opi[g][q];
+                const int slot = pd.ops[g][q];
+                if (slot >= 0) {
+                    T d[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) d[k] = 0;
+                    adj_overlap<T, R>(pr, pi, lr, li, i, d);
+                    const T r = wave_transpose_reduce<T, 16>(d);
+                    if ((lane & 3) == 0) wacc[wave][slot][lane >> 2] += (double)r;
+                }
+                const int gi = pd.opg[g][q];
+                if (gi >= 0) {
+                    apply_op<T, R>(pr, pi, i, gates + 32 * gi);
+                    apply_op<T, R>(lr, li, i, gates + 32 * gi);
+                }
+            }
+            if (active) {
+#pragma unroll
+                for (int m = 0; m < (1 << R); ++m) {
+                    const uint32_t idx = fl_swz(b0 | ((uint32_t)m << u0));
+                    cplx a, b;
+                    a.x = pr[m];
+                    a.y = pi[m];
+                    b.x = lr[m];
+                    b.y = li[m];
+                    lp[idx] = a;
+                    ll[idx] = b;
+                }
+            }
+            __syncthreads();
+        }
+        tile_store<T, KT>(psi, base, K, C, h, lp);
+        tile_store<T, KT>(lam, base, K, C, h, ll);
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < pd.nslots * 16; t += FL_NT) {
+        const int sl = t >> 4, v = t & 15;
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < FL_NT / 64; ++w) s += wacc[w][sl][v];
+        double* dst = Mpart + ((size_t)blockIdx.x * nbonds + pd.sbond[sl]) * 16 + v;
+        *dst += s;
+    }
+}
+
+__global__ void k_zero(double* __restrict__ p, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+
+static inline uint32_t ntiles_of(const fl_geom& g) { return 1u << (g.L - g.K); }
+
+hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gates, const fl_pass& pd,
+                        hipStream_t s) {
+    const dim3 grid(ntiles_of(g)), block(FL_NT);
+    if (dtype == 0) {
+        float2* p = (float2*)psi;
+        const float* G = (const float*)gates;
+        if (g.K == FL_KMAX_C64 && g.R == 4)
+            hipLaunchKernelGGL((k_sweep<float, 4, FL_KMAX_C64, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else if (g.R == 4)
+            hipLaunchKernelGGL((k_sweep<float, 4, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else if (g.R == 3)
+            hipLaunchKernelGGL((k_sweep<float, 3, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else
+            hipLaunchKernelGGL((k_sweep<float, 2, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
+    } else {
+        double2* p = (double2*)psi;
+        const double* G = (const double*)gates;
+        if (g.K == FL_KMAX_C128 && g.R == 4)
+            hipLaunchKernelGGL((k_sweep<double, 4, FL_KMAX_C128, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else if (g.R == 4)
+            hipLaunchKernelGGL((k_sweep<double, 4, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else if (g.R == 3)
+            hipLaunchKernelGGL((k_sweep<double, 3, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        else
+            hipLaunchKernelGGL((k_sweep<double, 2, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
+                      int nslot, hipStream_t s) {
+    const uint32_t nt = ntiles_of(g);
+    if (dtype == 0) {
+        const float2* p = (const float2*)psi;
+        if (g.K == FL_KMAX_C64)
+            hipLaunchKernelGGL((k_rdm<float, FL_KMAX_C64, FL_KMAX_C64>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt,
+                               pd, partials, nslot);
+        else
+            hipLaunchKernelGGL((k_rdm<float, 0, FL_KMAX_C64>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
+                               partials, nslot);
+    } else {
+        const double2* p = (const double2*)psi;
+        if (g.K == FL_KMAX_C128)
+            hipLaunchKernelGGL((k_rdm<double, FL_KMAX_C128, FL_KMAX_C128>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W,
+                               nt, pd, partials, nslot);
+        else
+            hipLaunchKernelGGL((k_rdm<double, 0, FL_KMAX_C128>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
+                               partials, nslot);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* partials, int nblocks, int nvals, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((nvals + 255) / 256), dim3(256), 0, s, partials, nblocks, nvals, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int dtype, void* psi, int L, const void* tabs, int a, int b, hipStream_t s) {
+    const uint64_t n = 1ull << L;
+    const double2* t = (const double2*)tabs;
+    const double2* tlo = t;
+    const double2* tmid = t + (1 << a);
+    const double2* thi = tmid + (1 << b);
+    const uint64_t want = (n + 255) / 256;
+    const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, s, (float2*)psi, tlo, tmid, thi, a, b, n);
+    else
+        hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, s, (double2*)psi, tlo, tmid, thi, a, b, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_overlap(int dta, const void* a, int dtb, const void* b, uint64_t n, double* partials, int grid,
+                          hipStream_t s) {
+    if (dta == 1 && dtb == 0)
+        hipLaunchKernelGGL((k_overlap<double, float>), dim3(grid), dim3(256), 0, s, (const double2*)a, (const float2*)b,
+                           n, partials);
+    else if (dta == 1 && dtb == 1)
+        hipLaunchKernelGGL((k_overlap<double, double>), dim3(grid), dim3(256), 0, s, (const double2*)a,
+                           (const double2*)b, n, partials);
+    else if (dta == 0 && dtb == 1)
+        hipLaunchKernelGGL((k_overlap<float, double>), dim3(grid), dim3(256), 0, s, (const float2*)a,
+                           (const double2*)b, n, partials);
+    else
+        hipLaunchKernelGGL((k_overlap<float, float>), dim3(grid), dim3(256), 0, s, (const float2*)a, (const float2*)b,
+                           n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_h(int dtype, const fl_geom& g, const void* psi, void* lam, const void* hmat, const fl_pass& pd,
+                          int first, hipStream_t s) {
+    const dim3 grid(ntiles_of(g)), block(FL_NT);
+    if (dtype == 0) {
+        if (g.K == FL_KMAX_C64)
+            hipLaunchKernelGGL((k_apply_h<float, FL_KMAX_C64, FL_KMAX_C64>), grid, block, 0, s, (const float2*)psi,
+                               (float2*)lam, (const float*)hmat, g.C, g.W, pd, first);
+        else
+            hipLaunchKernelGGL((k_apply_h<float, 0, FL_KMAX_C64>), grid, block, 0, s, (const float2*)psi,
+                               (float2*)lam, (const float*)hmat, g.C, g.W, pd, first);
+    } else {
+        if (g.K == FL_KMAX_C128)
+            hipLaunchKernelGGL((k_apply_h<double, FL_KMAX_C128, FL_KMAX_C128>), grid, block, 0, s,
+                               (const double2*)psi, (double2*)lam, (const double*)hmat, g.C, g.W, pd, first);
+        else
+            hipLaunchKernelGGL((k_apply_h<double, 0, FL_KMAX_C128>), grid, block, 0, s, (const double2*)psi,
+                               (double2*)lam, (const double*)hmat, g.C, g.W, pd, first);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, const void* gates, const fl_pass& pd,
+                          double* Mpart, int grid, hipStream_t s) {
+    const uint32_t nt = ntiles_of(g);
+    const int nb = g.L - 1;
+    if (dtype == 0) {
+        float2* p = (float2*)psi;
+        float2* l = (float2*)lam;
+        const float* G = (const float*)gates;
+        if (g.K == FL_KMAX_ADJ && g.R == 4)
+            hipLaunchKernelGGL((k_adjoint<float, 4, FL_KMAX_ADJ, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G,
+                               g.C, g.W, nt, pd, Mpart, nb);
+        else if (g.R == 4)
+            hipLaunchKernelGGL((k_adjoint<float, 4, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C, g.W,
+                               nt, pd, Mpart, nb);
+        else if (g.R == 3)
+            hipLaunchKernelGGL((k_adjoint<float, 3, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C, g.W,
+                               nt, pd, Mpart, nb);
+        else
+            hipLaunchKernelGGL((k_adjoint<float, 2, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C, g.W,
+                               nt, pd, Mpart, nb);
+    } else {
+        double2* p = (double2*)psi;
+        double2* l = (double2*)lam;
+        const double* G = (const double*)gates;
+        if (g.K == FL_KMAX_ADJ && g.R == 4)
+            hipLaunchKernelGGL((k_adjoint<double, 4, FL_KMAX_ADJ, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l,
+                               G, g.C, g.W, nt, pd, Mpart, nb);
+        else if (g.R == 4)
+            hipLaunchKernelGGL((k_adjoint<double, 4, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C,
+                               g.W, nt, pd, Mpart, nb);
+        else if (g.R == 3)
+            hipLaunchKernelGGL((k_adjoint<double, 3, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C,
+                               g.W, nt, pd, Mpart, nb);
+        else
+            hipLaunchKernelGGL((k_adjoint<double, 2, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C,
+                               g.W, nt, pd, Mpart, nb);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* p, uint64_t n, hipStream_t s) {
+    const uint64_t want = (n + 255) / 256;
+    const unsigned grid = (unsigned)(want < 4096 ? (want ? want : 1) : 4096);
+    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace fl

@@ -1,0 +1,117 @@
+"""Convenience wrappers over the C ABI: an engine object and the
+torch.autograd.Function whose backward is the library's adjoint pass."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (fl_apply_period, fl_create, fl_energy_spread, fl_expect_energy, fl_grad, fl_init_state,
+               fl_overlap, fl_set_bonds, fl_xyz_bonds, fl_xyz_generators, new_state)
+
+
+class FloquetEngine:
+    """One chain length, one precision, one variant; states are torch tensors."""
+
+    def __init__(self, L: int, dtype: str = "c64", variant: str = "plain"):
+        self.L = L
+        self.ctx = fl_create(L, dtype, variant)
+
+    def set_bonds(self, h, T: float):
+        fl_set_bonds(self.ctx, h, T)
+
+    def set_xyz(self, J, fields, T: float):
+        self.set_bonds(fl_xyz_bonds(self.L, J, fields), T)
+
+    def new_state(self):
+        return new_state(self.ctx)
+
+    def init(self, psi, spinors):
+        fl_init_state(self.ctx, psi, spinors)
+
+    def step(self, psi, n: int = 1, dagger: bool = False):
+        fl_apply_period(self.ctx, psi, n, dagger)
+
+    def energy(self, psi):
+        return fl_expect_energy(self.ctx, psi)
+
+    def energy_density(self, psi) -> float:
+        E, N = fl_expect_energy(self.ctx, psi)
+        return E / (self.L * N)
+
+    def energy_spread(self, psi, ws):
+        """(sigma_E, <H0>, <H0^2>) of the normalised state (Sec. IV, Eq. (10)-(11))."""
+        E, E2, N = fl_energy_spread(self.ctx, psi, ws)
+        e, e2 = E / N, E2 / N
+        return float(np.sqrt(max(e2 - e * e, 0.0))), e, e2
+
+    def overlap(self, phi, psi):
+        return fl_overlap(self.ctx, phi, psi)
+
+    def run(self, psi, n: int, every: int):
+        """Evolve n periods, recording (period, e, <H0>/L, N) every `every` periods."""
+        rows = []
+        E, N = self.energy(psi)
+        rows.append((0, E / (self.L * N), E / self.L, N))
+        t = 0
+        while t < n:
+            k = min(every, n - t)
+            self.step(psi, k)
+            t += k
+            E, N = self.energy(psi)
+            rows.append((t, E / (self.L * N), E / self.L, N))
+        return rows
+
+
+def _torch():
+    import torch
+    return torch
+
+
+class FloquetEnergy:
+    """E_n(J, T) = <psi_n|H0|psi_n> of the XYZ-plus-fields chain as a
+    differentiable torch function of the couplings J (L-1, 3) and the period T.
+
+    forward evolves on the GPU, storing the state every K periods; backward
+    runs the library's reverse pass (G^dagger replay from those checkpoints).
+    Each forward supports one backward (the saved state is consumed).
+
+        E = FloquetEnergy.apply(J, T, engine, fields, spinors, n, K)
+    """
+
+    @staticmethod
+    def _fn():
+        torch = _torch()
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, J, T, engine, fields, spinors, n, K):
+                L = engine.L
+                Jn = J.detach().cpu().numpy().astype(np.float64)
+                engine.set_xyz(Jn, fields, float(T))
+                psi = engine.new_state()
+                engine.init(psi, spinors)
+                ckpts = []
+                if K > 0:
+                    for _ in range(n // K):
+                        ckpts.append(psi.clone())
+                        engine.step(psi, K)
+                else:
+                    engine.step(psi, n)
+                E, _ = engine.energy(psi)
+                ctx.engine, ctx.psi, ctx.ckpts, ctx.n, ctx.K, ctx.L = engine, psi, ckpts, n, K, L
+                return torch.tensor(E, dtype=torch.float64)
+
+            @staticmethod
+            def backward(ctx, gE):
+                eng = ctx.engine
+                lam = torch.empty_like(ctx.psi)
+                g = fl_grad(eng.ctx, ctx.psi, ctx.ckpts, ctx.n, ctx.K, fl_xyz_generators(ctx.L), lam)
+                ctx.psi = ctx.ckpts = None
+                gJ = torch.from_numpy(g[:-1].reshape(ctx.L - 1, 3).copy()) * gE
+                gT = torch.tensor(g[-1], dtype=torch.float64) * gE
+                return gJ, gT, None, None, None, None, None
+
+        return _F
+
+    @classmethod
+    def apply(cls, J, T, engine, fields, spinors, n, K):
+        return cls._fn().apply(J, T, engine, fields, spinors, n, K)

@@ -1,0 +1,358 @@
+"""GPU parity of the HIP path against the FP64 oracle (MI355X only).
+
+Every call goes through the C ABI.  Small chains are compared element by
+element; full-size chains (L = 30, the benchmark's plan and launch shapes) are
+compared on outputs the oracle can compute exactly: bond density matrices of
+a light-cone subchain, closed forms and the echo.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import floquet_inputs as fin
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2111_08044_amd as fl  # noqa: E402
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _gpu_state(ctx, vec=None):
+    psi = fl.new_state(ctx)
+    if vec is not None:
+        psi.copy_(torch.from_numpy(np.asarray(vec, dtype=np.complex128)).to(psi.dtype))
+    return psi
+
+
+def _model(L, seed=fin.DEFAULT_SEED, T=0.25):
+    w = fin.xyz_workload(L, seed=seed, T=T)
+    hs = O.xyz_bond_hamiltonians(L, w["J"], w["fields"])
+    return w, hs
+
+
+# ----------------------------------------------------------------- C1 parity
+
+def test_c1_fp64_state_and_energy_over_1000_periods():
+    """L = 12 complex128, identical FP64 gates on both sides: the state after
+    1000 periods within 1e-12 in L2 and e(t) within 1e-12 every period."""
+    L, n = 12, 1000
+    say("case: C1 fp64 L=12 n=1000")
+    w, hs = _model(L)
+    G = O.floquet_gates(hs, w["T"])
+    ctx = fl.fl_create(L, "c128")
+    fl.fl_set_gates(ctx, G, hs, w["T"])
+    psi = _gpu_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ref = O.product_state(w["spinors"])
+    assert np.linalg.norm(psi.cpu().numpy() - ref) < 1e-15
+    worst_e = 0.0
+    for t in range(1, n + 1):
+        fl.fl_apply_period(ctx, psi, 1)
+        ref = O.floquet_period(ref, L, G)
+        E, N = fl.fl_expect_energy(ctx, psi)
+        Er, Nr = O.energy(ref, L, hs)
+        worst_e = max(worst_e, abs(E / (L * N) - Er / (L * Nr)))
+    err = np.linalg.norm(psi.cpu().numpy() - ref)
+    say(f"C1 fp64: state L2 {err:.3e}, worst e {worst_e:.3e}, |N-1| {abs(N - 1):.3e}")
+    assert err < 1e-12
+    assert worst_e < 1e-12
+    assert abs(N - 1.0) < 1e-13
+
+
+def test_c1_fp32_energy_density_after_1000_periods():
+    """L = 12 complex64 with the library's own gates (fl_set_bonds): energy
+    density within 1e-5 of the oracle every 10 periods up to 1000."""
+    L, n = 12, 1000
+    say("case: C1 fp32 L=12 n=1000")
+    w, hs = _model(L)
+    ctx = fl.fl_create(L, "c64")
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, w["J"], w["fields"]), w["T"])
+    psi = _gpu_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    _, rows = O.run_energy_series(L, hs, w["T"], w["spinors"], n, every=10)
+    worst = 0.0
+    for t, e_ref, _, _ in rows:
+        if t > 0:
+            fl.fl_apply_period(ctx, psi, 10)
+        E, N = fl.fl_expect_energy(ctx, psi)
+        worst = max(worst, abs(E / (L * N) - e_ref))
+    say(f"C1 fp32: worst |e - e_ref| {worst:.3e}, final |N-1| {abs(N - 1):.3e}")
+    assert worst < 1e-5
+
+
+# ----------------------------------------------------- small and ragged chains
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("L", [2, 3, 4, 5, 9, 13, 14, 15, 17])
+def test_small_chains_element_by_element(dtype, L):
+    """Single-tile, multi-tile and ragged plans (n = 1, 7, 17 so that blocks of
+    16 periods and remainders both run) against the oracle."""
+    say(f"case: small L={L} {dtype}")
+    w, hs = _model(L, seed=100 + L)
+    G = O.floquet_gates(hs, w["T"])
+    ctx = fl.fl_create(L, dtype)
+    fl.fl_set_gates(ctx, G, hs, w["T"])
+    psi = _gpu_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ref = O.product_state(w["spinors"])
+    tol = 1e-12 if dtype == "c128" else 3e-6
+    for n in (1, 7, 17):
+        fl.fl_apply_period(ctx, psi, n)
+        ref = O.evolve(ref, L, G, n)
+        got = psi.cpu().numpy().astype(np.complex128)
+        assert np.max(np.abs(got - ref)) < tol, (n, np.max(np.abs(got - ref)))
+    # and back with U_F^dagger
+    fl.fl_apply_period(ctx, psi, 25, dagger=True)
+    ref = O.product_state(w["spinors"])
+    got = psi.cpu().numpy().astype(np.complex128)
+    assert np.max(np.abs(got - ref)) < 10 * tol
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("L", [2, 6, 13, 16])
+def test_rdm_energy_and_spread_match_oracle(dtype, L):
+    say(f"case: rdm L={L} {dtype}")
+    w, hs = _model(L, seed=7)
+    rng = np.random.default_rng(L)
+    v = rng.standard_normal(1 << L) + 1j * rng.standard_normal(1 << L)
+    ctx = fl.fl_create(L, dtype)
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = _gpu_state(ctx, v)
+    vv = psi.cpu().numpy().astype(np.complex128)   # what the GPU actually holds
+    E, N, rho = fl.fl_expect_energy(ctx, psi, rdm=True)
+    Er, Nr = O.energy(vv, L, hs)
+    rtol = 1e-13 if dtype == "c128" else 1e-12
+    assert abs(N - Nr) < rtol * Nr
+    assert abs(E - Er) < rtol * Nr * L
+    for b in range(L - 1):
+        assert np.max(np.abs(rho[b] - O.bond_rdm(vv, L, b))) < rtol * Nr
+    ws = _gpu_state(ctx)
+    E1, E2, N2 = fl.fl_energy_spread(ctx, psi, ws)
+    hv = O.apply_h0(vv, L, hs)
+    assert abs(E1 - np.vdot(vv, hv).real) < 1e-5 * Nr * L
+    assert abs(E2 - np.vdot(hv, hv).real) < 1e-5 * np.vdot(hv, hv).real
+    if dtype == "c128":
+        assert np.max(np.abs(ws.cpu().numpy() - hv)) < 1e-12 * np.max(np.abs(hv))
+
+
+def test_overlap_mixed_precision():
+    L = 15
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(1 << L) + 1j * rng.standard_normal(1 << L)
+    b = rng.standard_normal(1 << L) + 1j * rng.standard_normal(1 << L)
+    ctx = fl.fl_create(L, "c64")
+    ta = torch.from_numpy(a).cuda()                      # complex128
+    tb = torch.from_numpy(b).to(torch.complex64).cuda()  # complex64
+    bb = tb.cpu().numpy().astype(np.complex128)
+    ov, na, nb = fl.fl_overlap(ctx, ta, tb)
+    assert abs(ov - np.vdot(a, bb)) < 1e-12 * np.sqrt(na * nb)
+    assert abs(na - np.vdot(a, a).real) < 1e-12 * na
+    assert abs(nb - np.vdot(bb, bb).real) < 1e-12 * nb
+
+
+# ------------------------------------------- full size (L = 30, bench plan)
+
+def _lightcone_rdm(L, hs, G, spinors, n, b):
+    """rho_b after n periods from the oracle on the subchain that holds the
+    backward light cone of bond b (2n sites each side; even start keeps the
+    layer parity of every bond)."""
+    lo = max(0, b - 2 * n - 1)
+    lo -= lo % 2
+    hi = min(L - 1, b + 1 + 2 * n + 1)
+    Ls = hi - lo + 1
+    psi = O.product_state(spinors[lo:hi + 1])
+    psi = O.evolve(psi, Ls, G[lo:hi], n)
+    return O.bond_rdm(psi, Ls, b - lo)
+
+
+@pytest.mark.parametrize("n", [3])
+def test_L30_lightcone_rdms_fp32(n):
+    """L = 30 complex64 through the benchmark's plan and kernels: bond density
+    matrices after n periods against the oracle on light-cone subchains."""
+    L = 30
+    say(f"case: L=30 light cone n={n}")
+    w, hs = _model(L)
+    G = O.floquet_gates(hs, w["T"])
+    ctx = fl.fl_create(L, "c64")
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, w["J"], w["fields"]), w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    fl.fl_apply_period(ctx, psi, n)
+    E, N, rho = fl.fl_expect_energy(ctx, psi, rdm=True)
+    worst = 0.0
+    for b in (0, 1, 6, 11, 12, 13, 14, 19, 20, 27, 28):
+        ref = _lightcone_rdm(L, hs, G, w["spinors"], n, b)
+        worst = max(worst, np.max(np.abs(rho[b] - ref)))
+    say(f"L=30 light-cone rdm worst {worst:.3e}, |N-1| {abs(N - 1):.3e}")
+    assert worst < 2e-6
+    assert abs(N - 1) < 1e-5
+    del psi
+    torch.cuda.empty_cache()
+
+
+def test_L30_swap_point_and_ising_closed_forms():
+    """Closed forms at full size: the SWAP point permutes the spinors (pins
+    layer order, bit order and tile mapping); the diagonal chain conserves E."""
+    L, n = 30, 5
+    say("case: L=30 swap/ising")
+    w = fin.xyz_workload(L, seed=5)
+    ctx = fl.fl_create(L, "c64")
+    J = np.full_like(w["J"], 2 * np.pi)
+    f0 = np.zeros_like(w["fields"])
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, J, f0), 0.25)
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    fl.fl_apply_period(ctx, psi, n)
+    order = list(range(L))
+    for _ in range(n):
+        for parity in (1, 0):
+            for b in range(parity, L - 1, 2):
+                order[b], order[b + 1] = order[b + 1], order[b]
+    phase = np.exp(-1j * np.pi / 4 * (L - 1) * n)
+    rng = np.random.default_rng(0)
+    xs = rng.integers(0, 1 << L, 4096)
+    got = psi[torch.from_numpy(xs).cuda()].cpu().numpy().astype(np.complex128)
+    sp = [w["spinors"][order[j]] for j in range(L)]
+    ref = np.array([phase * np.prod([sp[j][(x >> (L - 1 - j)) & 1] for j in range(L)]) for x in xs])
+    assert np.max(np.abs(got - ref)) < 2e-6
+    # diagonal chain: E conserved
+    J2 = w["J"].copy(); J2[:, :2] = 0
+    f2 = w["fields"].copy(); f2[:, :2] = 0
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, J2, f2), 0.25)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    E0, N0 = fl.fl_expect_energy(ctx, psi)
+    fl.fl_apply_period(ctx, psi, 20)
+    E1, N1 = fl.fl_expect_energy(ctx, psi)
+    assert abs(E0 - E1) < 1e-5 * L and abs(N1 - 1) < 1e-5
+    del psi
+    torch.cuda.empty_cache()
+
+
+def test_L30_echo_fp32():
+    """U_F^dagger^n U_F^n psi0 = psi0 at full size (Sec. V echo)."""
+    L, n = 30, 10
+    say("case: L=30 echo")
+    w, hs = _model(L)
+    ctx = fl.fl_create(L, "c64")
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, w["J"], w["fields"]), w["T"])
+    psi = fl.new_state(ctx)
+    psi0 = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi0, w["spinors"])
+    psi.copy_(psi0)
+    fl.fl_apply_period(ctx, psi, n)
+    fl.fl_apply_period(ctx, psi, n, dagger=True)
+    ov, n0, n1 = fl.fl_overlap(ctx, psi0, psi)
+    say(f"L=30 echo overlap error {abs(1 - ov):.3e}")
+    assert abs(1 - ov) < 1e-5
+    del psi, psi0
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------- gradient
+
+@pytest.mark.parametrize("L,n,K", [(2, 3, 0), (5, 4, 2), (10, 20, 5), (13, 8, 4), (14, 6, 3)])
+def test_gradient_fp64_matches_oracle_adjoint(L, n, K):
+    say(f"case: grad fp64 L={L} n={n} K={K}")
+    w, hs = _model(L, seed=31)
+    G = O.floquet_gates(hs, w["T"])
+    gens = O.xyz_coupling_generators(L)
+    psi0 = O.product_state(w["spinors"])
+    ref, Eref = O.adjoint_gradient(L, hs, gens, w["T"], psi0, n)
+    ctx = fl.fl_create(L, "c128")
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ck = []
+    if K:
+        for _ in range(n // K):
+            ck.append(psi.clone())
+            fl.fl_apply_period(ctx, psi, K)
+    else:
+        fl.fl_apply_period(ctx, psi, n)
+    lam = torch.empty_like(psi)
+    g = fl.fl_grad(ctx, psi, ck, n, K, gens, lam)
+    err = np.max(np.abs(g - ref)) / max(1.0, np.max(np.abs(ref)))
+    say(f"grad fp64 L={L}: rel err {err:.3e}")
+    assert err < 1e-10
+
+
+def test_gradient_fp32_L12_close_to_fp64():
+    L, n, K = 12, 40, 10
+    say("case: grad fp32 L=12")
+    w, hs = _model(L, seed=37)
+    gens = O.xyz_coupling_generators(L)
+    ref, _ = O.adjoint_gradient(L, hs, gens, w["T"], O.product_state(w["spinors"]), n)
+    ctx = fl.fl_create(L, "c64")
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ck = []
+    for _ in range(n // K):
+        ck.append(psi.clone())
+        fl.fl_apply_period(ctx, psi, K)
+    g = fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi))
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    say(f"grad fp32 L=12: rel err {err:.3e}")
+    assert err < 1e-4
+
+
+def test_autograd_function_matches_oracle():
+    L, n, K = 8, 12, 4
+    w, hs = _model(L, seed=41)
+    eng = fl.FloquetEngine(L, "c128")
+    J = torch.tensor(w["J"], dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(w["T"], dtype=torch.float64, requires_grad=True)
+    E = fl.FloquetEnergy.apply(J, T, eng, w["fields"], w["spinors"], n, K)
+    E.backward()
+    ref, Eref = O.adjoint_gradient(L, hs, O.xyz_coupling_generators(L), w["T"],
+                                   O.product_state(w["spinors"]), n)
+    assert abs(E.item() - Eref) < 1e-12
+    assert np.max(np.abs(J.grad.numpy().reshape(-1) - ref[:-1])) < 1e-10
+    assert abs(T.grad.item() - ref[-1]) < 1e-10
+
+
+# ----------------------------------------------------------------- ABI errors
+
+def test_abi_error_paths_launch_nothing():
+    L = 10
+    ctx = fl.fl_create(L, "c64")
+    psi = fl.new_state(ctx)
+    with pytest.raises(fl.FloquetError) as e:
+        fl.fl_apply_period(ctx, psi, 1)          # no bonds yet
+    assert e.value.code == -4
+    w, hs = _model(L)
+    bad = hs.copy()
+    bad[2, 0, 1] += 0.5                          # not Hermitian
+    with pytest.raises(fl.FloquetError) as e:
+        fl.fl_set_bonds(ctx, bad, 0.25)
+    assert e.value.code == -1
+    with pytest.raises(fl.FloquetError):
+        fl.fl_set_bonds(ctx, hs, -1.0)
+    fl.fl_set_bonds(ctx, hs, 0.25)
+    lib = fl.lib()
+    import ctypes as C
+    assert lib.fl_apply_period(ctx.handle, C.c_void_p(psi.data_ptr()), -1, 0) == -1
+    assert lib.fl_apply_period(ctx.handle, C.c_void_p(psi.data_ptr() + 8), 1, 0) == -1   # misaligned
+    host = np.zeros(1 << L, dtype=np.complex64)
+    assert lib.fl_apply_period(ctx.handle, C.c_void_p(host.ctypes.data), 1, 0) == -1      # host memory
+    assert lib.fl_apply_period(ctx.handle, None, 1, 0) == -1
+    with pytest.raises(fl.FloquetError):
+        fl.fl_create(35, "c64")
+    with pytest.raises(fl.FloquetError):
+        fl.fl_create(34, "c128")
+    lam = torch.empty_like(psi)
+    with pytest.raises(fl.FloquetError):
+        fl.fl_grad(ctx, psi, [psi.clone()], 10, 3, O.xyz_coupling_generators(L), lam)   # n % K != 0
