@@ -158,7 +158,7 @@ def main():
     bytes_ = 16.0 * (1 << L) * launches             # read + write of every amplitude per pass
     achieved_tflops = flops / (sweep_ms / 1e3) / 1e12
     achieved_gbps = bytes_ / (sweep_ms / 1e3) / 1e9
-    roof = {"kernel": "k_sweep<float,4,13>", "bound": "alu", "achieved": round(achieved_tflops, 3),
+    roof = {"kernel": "k_sweep_tiles<float,5,13,256>", "bound": "alu", "achieved": round(achieved_tflops, 3),
             "peak": round(PEAK_FP32_VALU, 2), "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU, 4),
             "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
             "flops_per_launch": flops / launches, "bytes_per_launch": bytes_ / launches,

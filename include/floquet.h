@@ -169,7 +169,8 @@ int fl_xyz_generators(int L, double *gens_out);
 int fl_tile_map(int L, int dtype, int h, uint64_t *out);
 
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
- * 1 = reverse sweep of the gradient, 2 = energy cover), flattened as int32:
+ * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover,
+ * 3 = cover used for H0 psi), flattened as int32:
  * [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {i, gate, slot}*}*}*].
  * Writes at most cap words to buf (may be NULL) and the required count to
  * *needed. */

@@ -55,7 +55,7 @@ size_t amp_bytes(int dtype) { return dtype == FL_C64 ? 8 : 16; }
 struct fl_ctx {
     int L = 0, dtype = 0, variant = 0, dev = 0;
     hipStream_t stream = nullptr;
-    fl_geom geom{}, geom_adj{};
+    fl_geom geom{}, geom_adj{}, geom_rdm{};
     bool have_gates = false, have_h = false;
     double T = 0.0;
     std::vector<cd> h, G;  // FP64, (L-1) x 16
@@ -68,7 +68,8 @@ struct fl_ctx {
     double* d_mpart = nullptr; // gradient partials [kAdjGrid][L-1][16]
     std::map<std::pair<int, int>, std::vector<fl_pass>> plans;
     std::map<int, std::vector<fl_pass>> adj_plans;
-    std::vector<fl_pass> cover;
+    std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
+    std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
 };
 
 namespace {
@@ -167,9 +168,9 @@ void rho_from16(const double* v, cd* rho) {
 }
 
 int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
-    const int grid = (int)std::min<uint32_t>(ntiles(c->geom), kReduceGrid);
-    for (const fl_pass& p : c->cover) {
-        hipError_t e = fl::launch_rdm(c->dtype, c->geom, psi, p, c->d_part, grid, c->L, c->stream);
+    const int grid = (int)std::min<uint32_t>(ntiles(c->geom_rdm), kReduceGrid);
+    for (const fl_pass& p : c->cover_rdm) {
+        hipError_t e = fl::launch_rdm(c->dtype, c->geom_rdm, psi, p, c->d_part, grid, c->L, c->stream);
         if (e != hipSuccess) return fail_hip(e, "k_rdm launch");
     }
     *grid_out = grid;
@@ -255,9 +256,11 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->variant = variant;
     c->dev = dev;
     c->stream = (hipStream_t)hip_stream;
-    c->geom = fl::make_geom(L, kmax_of(dtype), 4);
+    c->geom = fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4);
     c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4);
+    c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
+    c->cover_rdm = fl::plan_cover(c->geom_rdm);
     const int nb = L - 1;
     const size_t rb = dtype == FL_C64 ? 4 : 8;
     hipError_t e = hipSuccess;
@@ -638,7 +641,7 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     std::vector<fl_pass> plan;
     fl_geom g;
     if (kind == 0) {
-        g = fl::make_geom(L, kmax_of(dtype), 4);
+        g = fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
         if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
@@ -654,10 +657,13 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
         for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
         plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 2) {
+        g = fl::make_geom(L, FL_KMAX_RDM, 2);
+        plan = fl::plan_cover(g);
+    } else if (kind == 3) {
         g = fl::make_geom(L, kmax_of(dtype), 4);
         plan = fl::plan_cover(g);
     } else {
-        return fail(FL_EINVAL, "kind must be 0, 1 or 2");
+        return fail(FL_EINVAL, "kind must be 0, 1, 2 or 3");
     }
     std::vector<int> words;
     fl::serialize_plan(g, plan, words);

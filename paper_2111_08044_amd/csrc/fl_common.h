@@ -34,7 +34,26 @@
 #define FL_KMAX_C64 13       // tile bits for complex64 (64 KiB of LDS)
 #define FL_KMAX_C128 12      // tile bits for complex128 (64 KiB of LDS)
 #define FL_KMAX_ADJ 12       // tile bits of the two-state adjoint pass (complex64)
+#define FL_KMAX_RDM 12       // tile bits of the energy / density-matrix reduction
 #define FL_MAX_SLOTS 16      // distinct reduction slots per pass
+#ifndef FL_SWEEP_NT_C64
+#define FL_SWEEP_NT_C64 256  // threads per workgroup of the complex64 full-tile sweep
+#endif
+#ifndef FL_SWEEP_R_C64
+#define FL_SWEEP_R_C64 5     // register bits per group of the complex64 sweep
+#endif
+#ifndef FL_PERSIST_WG
+#define FL_PERSIST_WG 512    // workgroups of the persistent full-tile sweep (2 per CU)
+#endif
+#ifndef FL_SWEEP_PERSIST
+#define FL_SWEEP_PERSIST 0        // 1: FL_PERSIST_WG workgroups loop over the tiles
+#endif
+#ifndef FL_SWEEP_TILE_PREFETCH
+#define FL_SWEEP_TILE_PREFETCH 0  // 1: load the next tile into registers during the gates
+#endif
+#ifndef FL_SWEEP_GATE_PREFETCH
+#define FL_SWEEP_GATE_PREFETCH 1  // 1: fetch the next gate matrix during the current one
+#endif
 
 struct fl_pass {
     int32_t h;                               // first physical bit of the high window

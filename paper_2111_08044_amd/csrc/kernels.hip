@@ -13,6 +13,8 @@
 // into VGPRs, applies the group's 4x4 gates there and writes them back.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "fl_common.h"
 #include "kernels.h"
 
@@ -31,6 +33,7 @@ template <> struct CT<double> { typedef double2 c; };
 // R-2 register bits.  G holds 16 complex entries, row-major, (re, im) pairs.
 template <typename T, int R, int I>
 __device__ __forceinline__ void apply_pair(T (&vr)[1 << R], T (&vi)[1 << R], const T* __restrict__ G) {
+    __asm__ volatile("; gate on register bits %0" ::"i"(I));
     T g[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) g[k] = G[k];
@@ -60,6 +63,52 @@ __device__ __forceinline__ void apply_pair(T (&vr)[1 << R], T (&vi)[1 << R], con
             vi[b | (i << I)] = si;
         }
     }
+    __asm__ volatile("; end gate on register bits %0" ::"i"(I));
+}
+
+// Same, with the 16 complex gate entries already in registers (SGPRs: the
+// gate is uniform across the workgroup).
+// The empty asm markers carry the bit position as an immediate: they keep the
+// optimizer from merging the variants for different I into one body with
+// run-time register indices (which would force the arrays into scratch).
+template <typename T, int R, int I>
+__device__ __forceinline__ void apply_pair_g(T (&vr)[1 << R], T (&vi)[1 << R], const T (&g)[32]) {
+    __asm__ volatile("; gate on register bits %0" ::"i"(I));
+#pragma unroll
+    for (int c = 0; c < (1 << (R - 2)); ++c) {
+        const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+        T ar[4], ai[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            ar[l] = vr[b | (l << I)];
+            ai[l] = vi[b | (l << I)];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T sr = g[8 * i] * ar[0];
+            T si = g[8 * i] * ai[0];
+            sr = fma(-g[8 * i + 1], ai[0], sr);
+            si = fma(g[8 * i + 1], ar[0], si);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                sr = fma(g[8 * i + 2 * j], ar[j], sr);
+                sr = fma(-g[8 * i + 2 * j + 1], ai[j], sr);
+                si = fma(g[8 * i + 2 * j], ai[j], si);
+                si = fma(g[8 * i + 2 * j + 1], ar[j], si);
+            }
+            vr[b | (i << I)] = sr;
+            vi[b | (i << I)] = si;
+        }
+    }
+    __asm__ volatile("; end gate on register bits %0" ::"i"(I));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void apply_op_g(T (&vr)[1 << R], T (&vi)[1 << R], int i, const T (&g)[32]) {
+    if constexpr (R >= 2) if (i == 0) { apply_pair_g<T, R, 0>(vr, vi, g); return; }
+    if constexpr (R >= 3) if (i == 1) { apply_pair_g<T, R, 1>(vr, vi, g); return; }
+    if constexpr (R >= 4) if (i == 2) { apply_pair_g<T, R, 2>(vr, vi, g); return; }
+    if constexpr (R >= 5) if (i == 3) { apply_pair_g<T, R, 3>(vr, vi, g); return; }
 }
 
 template <typename T, int R>
@@ -190,6 +239,130 @@ __global__ __launch_bounds__(FL_NT) void k_sweep(typename CT<T>::c* __restrict__
     tile_store<T, KT>(psi, base, K, C, h, lds);
 }
 
+// Full-size tiles (K = KT): persistent workgroups walk tiles
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
+// issued into registers before the current tile's gates run, so HBM latency
+// hides behind the gate arithmetic (a workgroup barrier on gfx950 waits for
+// LDS traffic only, not for outstanding global loads).  Every thread holds
+// SUB register groups of 2^R amplitudes and applies each gate to all of
+// them; the next gate's matrix is fetched while the current one is applied.
+template <typename T, int R, int KT, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_sweep_tiles(typename CT<T>::c* __restrict__ psi,
+                                                    const T* __restrict__ gates, uint32_t ntiles, int W,
+                                                    fl_pass pd) {
+    typedef typename CT<T>::c cplx;
+    constexpr int C = FL_LOWBITS;
+    constexpr int K = KT;
+    constexpr int SUB = (1 << (K - R)) / NT;
+    static_assert(SUB >= 1, "tile too small for the workgroup");
+    constexpr int APL = (sizeof(T) == 4) ? 2 : 1;           // amplitudes per 16-byte access
+    constexpr int ITER = (1 << K) / (APL * NT);
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type v16;
+    __shared__ cplx lds[1 << K];
+    const int h = pd.h;
+    // Element j = APL (tid + s NT) of a tile sits at toff + s * tstride: APL NT
+    // is a multiple of 2^C, so s only moves the window part of the offset.
+    static_assert((APL * NT) % (1 << C) == 0 && (APL * NT) % 256 == 0, "tile access stride");
+    const uint64_t toff = fl_tile_offset(APL * threadIdx.x, C, h);
+    const uint64_t tstride = (uint64_t)((APL * NT) >> C) << h;
+    // LDS slot of element j + s APL NT is fl_swz(j) + s APL NT (the swizzle
+    // only mixes bits 0..7), and fl_swz(j + 1) = fl_swz(j) ^ 1 for even j.
+    const uint32_t l0 = fl_swz(APL * threadIdx.x);
+    v16 nxt[ITER];
+    uint32_t tile = blockIdx.x;
+    auto issue = [&](uint32_t t) {
+        const v16* src = reinterpret_cast<const v16*>(psi + fl_tile_base(t, C, W, h) + toff);
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) nxt[s] = *reinterpret_cast<const v16*>(
+            reinterpret_cast<const typename CT<T>::c*>(src) + s * tstride);
+    };
+    if (FL_SWEEP_TILE_PREFETCH && tile < ntiles) issue(tile);
+    const uint32_t tile_step = FL_SWEEP_PERSIST ? gridDim.x : ntiles;
+    for (; tile < ntiles; tile += tile_step) {
+        if (!FL_SWEEP_TILE_PREFETCH) issue(tile);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) {
+            const uint32_t l = l0 + s * (APL * NT);
+            if constexpr (sizeof(T) == 4) {
+                lds[l] = make_float2(nxt[s].x, nxt[s].y);
+                lds[l ^ 1] = make_float2(nxt[s].z, nxt[s].w);
+            } else {
+                lds[l] = nxt[s];
+            }
+        }
+        __syncthreads();
+        if (FL_SWEEP_TILE_PREFETCH && tile + tile_step < ntiles) issue(tile + tile_step);
+        for (int g = 0; g < pd.ngroups; ++g) {
+            const int u0 = pd.u0[g];
+            const int nops = pd.nops[g];
+            T vr[SUB][1 << R], vi[SUB][1 << R];
+            uint32_t b0[SUB];
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+                b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
+#pragma unroll
+                for (int m = 0; m < (1 << R); ++m) {
+                    const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
+                    vr[s][m] = a.x;
+                    vi[s][m] = a.y;
+                }
+            }
+            T gc[32];
+            {
+                const T* G = gates + 32 * pd.opg[g][0];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) gc[k] = G[k];
+            }
+            for (int q = 0; q < nops; ++q) {
+                const int i = pd.opi[g][q];
+                if constexpr (sizeof(T) == 4 && FL_SWEEP_GATE_PREFETCH) {
+                    // prefetch the next gate (32 SGPRs) while this one is applied
+                    const int qn = (q + 1 < nops) ? q + 1 : q;
+                    const T* Gn = gates + 32 * pd.opg[g][qn];
+                    T gn[32];
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) gn[k] = Gn[k];
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) gc[k] = gn[k];
+                } else {
+                    if (q > 0) {
+                        const T* G = gates + 32 * pd.opg[g][q];
+#pragma unroll
+                        for (int k = 0; k < 32; ++k) gc[k] = G[k];
+                    }
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+#pragma unroll
+                for (int m = 0; m < (1 << R); ++m) {
+                    cplx a;
+                    a.x = vr[s][m];
+                    a.y = vi[s][m];
+                    lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
+                }
+            }
+            __syncthreads();
+        }
+        cplx* dst = psi + fl_tile_base(tile, C, W, h) + toff;
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) {
+            const uint32_t l = l0 + s * (APL * NT);
+            if constexpr (sizeof(T) == 4) {
+                const float2 a = lds[l], b = lds[l ^ 1];
+                *reinterpret_cast<float4*>(dst + s * tstride) = make_float4(a.x, a.y, b.x, b.y);
+            } else {
+                *reinterpret_cast<v16*>(dst + s * tstride) = lds[l];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // wave-level reductions
 // ---------------------------------------------------------------------------
@@ -197,27 +370,31 @@ __global__ __launch_bounds__(FL_NT) void k_sweep(typename CT<T>::c* __restrict__
 // NV values per lane -> lane l returns the wave-wide sum of value index
 // l >> (6 - log2 NV).  Each step keeps one half of the values and trades the
 // other half with the partner lane, so the whole reduction costs
-// NV/2 + NV/4 + ... shuffles instead of NV * 6.
+// NV/2 + NV/4 + ... shuffles instead of NV * 6.  Written as a template
+// recursion so that every array index is a compile-time constant.
+template <typename T, int N, int D>
+__device__ __forceinline__ void tr_steps(T (&v)[N], int lane) {
+    if constexpr (N > 1) {
+        constexpr int H = N / 2;
+        const bool upper = (lane & D) != 0;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            const T keep = upper ? v[k + H] : v[k];
+            const T send = upper ? v[k] : v[k + H];
+            v[k] = keep + __shfl_xor(send, D);
+        }
+        tr_steps<T, H, D / 2>(*reinterpret_cast<T(*)[H]>(&v[0]), lane);
+    } else {
+#pragma unroll
+        for (int d = D; d >= 1; d >>= 1) v[0] += __shfl_xor(v[0], d);
+    }
+}
+
 template <typename T, int NV>
 __device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
-    const int lane = threadIdx.x & 63;
-    constexpr int LG = (NV >= 64) ? 6 : (NV >= 32) ? 5 : (NV >= 16) ? 4 : (NV >= 8) ? 3 : (NV >= 4) ? 2 : (NV >= 2) ? 1 : 0;
-#pragma unroll
-    for (int s = 0; s < LG; ++s) {
-        const int d = 32 >> s;
-        const int half = NV >> (s + 1);
-        const bool upper = (lane & d) != 0;
-#pragma unroll
-        for (int k = 0; k < half; ++k) {
-            const T keep = upper ? v[k + half] : v[k];
-            const T send = upper ? v[k] : v[k + half];
-            v[k] = keep + __shfl_xor(send, d);
-        }
-    }
-    T r = v[0];
-#pragma unroll
-    for (int d = (32 >> LG); d >= 1; d >>= 1) r += __shfl_xor(r, d);
-    return r;
+    static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
+    tr_steps<T, NV, 32>(v, threadIdx.x & 63);
+    return v[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -228,6 +405,7 @@ __device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
 // partials layout: [gridDim.x][nslot][16] doubles, slot = bond, slot L-1 = norm.
 
 #define FL_RDM_MAXG 16
+#define FL_RDM_TILE_MAXG 13   // bond slots of a full-tile cover pass (K-1 <= 12) + the norm
 
 template <typename T, int KT, int KMAX>
 __global__ __launch_bounds__(FL_NT) void k_rdm(const typename CT<T>::c* __restrict__ psi, int C, int W,
@@ -306,6 +484,103 @@ __global__ __launch_bounds__(FL_NT) void k_rdm(const typename CT<T>::c* __restri
             partials[((size_t)blockIdx.x * nslot + pd.ops[g][0]) * 16 + v] = s;
         } else if ((pd.flags & 1) && v == 0) {
             partials[((size_t)blockIdx.x * nslot + (nslot - 1)) * 16] = s;
+        }
+    }
+}
+
+// Full-size tiles: persistent workgroups with the next tile prefetched into
+// registers (as in k_sweep_tiles).  For complex64 states each lane sums its
+// products over one tile in FP32, the wave reduces those 16 partials in FP32,
+// and lanes then accumulate the per-tile sums in FP64 across tiles; complex128
+// states use FP64 throughout.
+template <typename T, int KT, int NT>
+__global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __restrict__ psi, int W, uint32_t ntiles,
+                                                  fl_pass pd, double* __restrict__ partials, int nslot) {
+    typedef typename CT<T>::c cplx;
+    constexpr int C = FL_LOWBITS;
+    constexpr int K = KT;
+    constexpr int APL = (sizeof(T) == 4) ? 2 : 1;
+    constexpr int ITER = (1 << K) / (APL * NT);
+    constexpr int NW = NT / 64;
+    constexpr int NG = FL_RDM_TILE_MAXG;
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type v16;
+    __shared__ cplx lds[1 << K];
+    __shared__ double wacc[NW][NG][16];
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t < NW * NG * 16; t += NT) (&wacc[0][0][0])[t] = 0.0;
+    double nrm = 0.0;
+    static_assert((APL * NT) % (1 << C) == 0 && (APL * NT) % 256 == 0, "tile access stride");
+    const uint64_t toff = fl_tile_offset(APL * threadIdx.x, C, h);
+    const uint64_t tstride = (uint64_t)((APL * NT) >> C) << h;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const cplx* src = psi + fl_tile_base(tile, C, W, h) + toff;
+        v16 v[ITER];
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) v[s] = *reinterpret_cast<const v16*>(src + s * tstride);
+        __syncthreads();
+        T tn = 0;
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) {
+            const uint32_t j = APL * (threadIdx.x + s * NT);
+            if constexpr (sizeof(T) == 4) {
+                lds[fl_swz(j)] = make_float2(v[s].x, v[s].y);
+                lds[fl_swz(j + 1)] = make_float2(v[s].z, v[s].w);
+                tn = fma(v[s].x, v[s].x, fma(v[s].y, v[s].y, fma(v[s].z, v[s].z, fma(v[s].w, v[s].w, tn))));
+            } else {
+                lds[fl_swz(j)] = v[s];
+                tn = fma(v[s].x, v[s].x, fma(v[s].y, v[s].y, tn));
+            }
+        }
+        nrm += (double)tn;
+        __syncthreads();
+        for (int g = 0; g < pd.ngroups; ++g) {
+            const int u = pd.u0[g];
+            T r[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) r[k] = 0;
+#pragma unroll 2
+            for (int s = 0; s < (1 << (K - 2)) / NT; ++s) {
+                const uint32_t b0 = fl_spread(threadIdx.x + s * NT, u, 2);
+                T ar[4], ai[4];
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const cplx a = lds[fl_swz(b0 | ((uint32_t)l << u))];
+                    ar[l] = a.x;
+                    ai[l] = a.y;
+                }
+#pragma unroll
+                for (int l = 0; l < 4; ++l) r[l] = fma(ar[l], ar[l], fma(ai[l], ai[l], r[l]));
+                int k = 4;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = i + 1; j < 4; ++j) {
+                        r[k] = fma(ar[i], ar[j], fma(ai[i], ai[j], r[k]));
+                        r[k + 1] = fma(ai[i], ar[j], fma(-ar[i], ai[j], r[k + 1]));
+                        k += 2;
+                    }
+            }
+            const T red = wave_transpose_reduce<T, 16>(r);
+            if ((lane & 3) == 0) wacc[wave][g][lane >> 2] += (double)red;
+        }
+    }
+    double nv[1] = {nrm};
+    const double ntot = wave_transpose_reduce<double, 1>(nv);
+    __syncthreads();
+    if (lane == 0) wacc[wave][NG - 1][0] = ntot;   // the norm uses the last slot row
+    __syncthreads();
+    for (int t = threadIdx.x; t < (pd.ngroups + 1) * 16; t += NT) {
+        const int g = t >> 4, v = t & 15;
+        const int gg = (g < pd.ngroups) ? g : NG - 1;
+        if (g == pd.ngroups && v > 0) continue;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += wacc[w][gg][v];
+        if (g < pd.ngroups) {
+            partials[((size_t)blockIdx.x * nslot + pd.ops[g][0]) * 16 + v] = sum;
+        } else if (pd.flags & 1) {
+            partials[((size_t)blockIdx.x * nslot + (nslot - 1)) * 16] = sum;
         }
     }
 }
@@ -475,7 +750,7 @@ __device__ __forceinline__ void adj_overlap(const T (&pr)[1 << R], const T (&pi)
 }
 
 template <typename T, int R, int KT, int KMAX>
-__global__ __launch_bounds__(FL_NT) void k_adjoint(typename CT<T>::c* __restrict__ psi,
+__global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint(typename CT<T>::c* __restrict__ psi,
                                                    typename CT<T>::c* __restrict__ lam, const T* __restrict__ gates,
                                                    int C, int W, uint32_t ntiles, fl_pass pd,
                                                    double* __restrict__ Mpart, int nbonds) {
@@ -573,8 +848,13 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
     if (dtype == 0) {
         float2* p = (float2*)psi;
         const float* G = (const float*)gates;
-        if (g.K == FL_KMAX_C64 && g.R == 4)
-            hipLaunchKernelGGL((k_sweep<float, 4, FL_KMAX_C64, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
+        if (g.K == FL_KMAX_C64 && g.W > 0) {
+            const uint32_t nt = ntiles_of(g);
+            const uint32_t pg = (FL_SWEEP_PERSIST && nt > FL_PERSIST_WG) ? FL_PERSIST_WG : nt;
+            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(pg),
+                               dim3(FL_SWEEP_NT_C64), 0, s, p, G, nt, g.W, pd);
+        } else if (g.R == 5)
+            hipLaunchKernelGGL((k_sweep<float, 5, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 4)
             hipLaunchKernelGGL((k_sweep<float, 4, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 3)
@@ -584,9 +864,12 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
     } else {
         double2* p = (double2*)psi;
         const double* G = (const double*)gates;
-        if (g.K == FL_KMAX_C128 && g.R == 4)
-            hipLaunchKernelGGL((k_sweep<double, 4, FL_KMAX_C128, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
-        else if (g.R == 4)
+        if (g.K == FL_KMAX_C128 && g.W > 0) {
+            const uint32_t nt = ntiles_of(g);
+            const uint32_t pg = (FL_SWEEP_PERSIST && nt > FL_PERSIST_WG) ? FL_PERSIST_WG : nt;
+            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256>), dim3(pg), dim3(256), 0, s, p, G, nt,
+                               g.W, pd);
+        } else if (g.R == 4)
             hipLaunchKernelGGL((k_sweep<double, 4, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 3)
             hipLaunchKernelGGL((k_sweep<double, 3, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
@@ -601,19 +884,19 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
     const uint32_t nt = ntiles_of(g);
     if (dtype == 0) {
         const float2* p = (const float2*)psi;
-        if (g.K == FL_KMAX_C64)
-            hipLaunchKernelGGL((k_rdm<float, FL_KMAX_C64, FL_KMAX_C64>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt,
-                               pd, partials, nslot);
+        if (g.K == FL_KMAX_RDM && g.W > 0)
+            hipLaunchKernelGGL((k_rdm_tiles<float, FL_KMAX_RDM, 256>), dim3(grid), dim3(256), 0, s, p, g.W, nt, pd,
+                               partials, nslot);
         else
-            hipLaunchKernelGGL((k_rdm<float, 0, FL_KMAX_C64>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
+            hipLaunchKernelGGL((k_rdm<float, 0, FL_KMAX_RDM>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
                                partials, nslot);
     } else {
         const double2* p = (const double2*)psi;
-        if (g.K == FL_KMAX_C128)
-            hipLaunchKernelGGL((k_rdm<double, FL_KMAX_C128, FL_KMAX_C128>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W,
-                               nt, pd, partials, nslot);
+        if (g.K == FL_KMAX_RDM && g.W > 0)
+            hipLaunchKernelGGL((k_rdm_tiles<double, FL_KMAX_RDM, 256>), dim3(grid), dim3(256), 0, s, p, g.W, nt, pd,
+                               partials, nslot);
         else
-            hipLaunchKernelGGL((k_rdm<double, 0, FL_KMAX_C128>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
+            hipLaunchKernelGGL((k_rdm<double, 0, FL_KMAX_RDM>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
                                partials, nslot);
     }
     return hipGetLastError();
