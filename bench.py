@@ -32,6 +32,25 @@ PEAK_FP32_PUBLISHED = 157.3        # TFLOP/s, counts packed dual-FP32 FMAs
 PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
+# HBM bytes per sweep launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
+# WRITE_SIZE) of "bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint
+# --calibrate-copy", each scaled by what the counter reads for the plain 8 GiB
+# device copy in the same run (FETCH_SIZE read 4.0 GiB -> x2; WRITE_SIZE read
+# 8.0 GiB -> x1).  Valid only for the kernel source it was taken on.
+TRAFFIC = {"kernels_sha256_16": "5c4356ae130362fe", "fetch_gib_raw": 4.0, "fetch_scale": 2.0,
+           "write_gib_raw": 8.0, "write_scale": 1.0}
+
+
+def measured_traffic():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2111_08044_amd", "csrc", "kernels.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != TRAFFIC["kernels_sha256_16"]:
+        return None
+    gib = TRAFFIC["fetch_gib_raw"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_gib_raw"] * TRAFFIC["write_scale"]
+    return gib * 2**30
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,6 +61,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also copy the state once (a plain device copy of known size, the reference "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -124,6 +146,11 @@ def main():
     eng.set_xyz(w["J"], w["fields"], w["T"])
     psi = eng.new_state()
     eng.init(psi, w["spinors"])
+    if args.calibrate_copy:
+        tmp = torch.empty_like(psi)
+        tmp.copy_(psi)
+        torch.cuda.synchronize()
+        del tmp
     e_series = []
     for _ in range(args.warmup):
         eng.step(psi, m)
@@ -160,7 +187,7 @@ def main():
     achieved_gbps = bytes_ / (sweep_ms / 1e3) / 1e9
     roof = {"kernel": "k_sweep_tiles<float,5,13,256>", "bound": "alu", "achieved": round(achieved_tflops, 3),
             "peak": round(PEAK_FP32_VALU, 2), "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_VALU, 4),
-            "traffic": None, "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "traffic": measured_traffic(), "avg_launch_ms": round(avg_launch_s * 1e3, 4),
             "flops_per_launch": flops / launches, "bytes_per_launch": bytes_ / launches,
             "hbm_gbps": round(achieved_gbps, 1), "hbm_frac": round(achieved_gbps / PEAK_HBM_GBPS, 4),
             "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4),

@@ -51,6 +51,9 @@
 #ifndef FL_SWEEP_TILE_PREFETCH
 #define FL_SWEEP_TILE_PREFETCH 0  // 1: load the next tile into registers during the gates
 #endif
+#ifndef FL_SWEEP_PINGPONG
+#define FL_SWEEP_PINGPONG 0       // 1: gates alternate between two register copies (no moves)
+#endif
 #ifndef FL_SWEEP_GATE_PREFETCH
 #define FL_SWEEP_GATE_PREFETCH 1  // 1: fetch the next gate matrix during the current one
 #endif

@@ -111,6 +111,45 @@ __device__ __forceinline__ void apply_op_g(T (&vr)[1 << R], T (&vi)[1 << R], int
     if constexpr (R >= 5) if (i == 3) { apply_pair_g<T, R, 3>(vr, vi, g); return; }
 }
 
+// Out-of-place form: reads every amplitude of (sr, si) and writes the result
+// to (dr, di).  All variants write the same destination registers, so the
+// run-time choice of I needs no register moves where the variants rejoin.
+template <typename T, int R, int I>
+__device__ __forceinline__ void apply_pair_to(const T (&sr)[1 << R], const T (&si)[1 << R], T (&dr)[1 << R],
+                                              T (&di)[1 << R], const T (&g)[32]) {
+    __asm__ volatile("; gate on register bits %0 (out of place)" ::"i"(I));
+#pragma unroll
+    for (int c = 0; c < (1 << (R - 2)); ++c) {
+        const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            T ar = g[8 * i] * sr[b];
+            T ai = g[8 * i] * si[b];
+            ar = fma(-g[8 * i + 1], si[b], ar);
+            ai = fma(g[8 * i + 1], sr[b], ai);
+#pragma unroll
+            for (int j = 1; j < 4; ++j) {
+                ar = fma(g[8 * i + 2 * j], sr[b | (j << I)], ar);
+                ar = fma(-g[8 * i + 2 * j + 1], si[b | (j << I)], ar);
+                ai = fma(g[8 * i + 2 * j], si[b | (j << I)], ai);
+                ai = fma(g[8 * i + 2 * j + 1], sr[b | (j << I)], ai);
+            }
+            dr[b | (i << I)] = ar;
+            di[b | (i << I)] = ai;
+        }
+    }
+    __asm__ volatile("; end gate on register bits %0 (out of place)" ::"i"(I));
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void apply_op_to(const T (&sr)[1 << R], const T (&si)[1 << R], T (&dr)[1 << R],
+                                            T (&di)[1 << R], int i, const T (&g)[32]) {
+    if constexpr (R >= 2) if (i == 0) { apply_pair_to<T, R, 0>(sr, si, dr, di, g); return; }
+    if constexpr (R >= 3) if (i == 1) { apply_pair_to<T, R, 1>(sr, si, dr, di, g); return; }
+    if constexpr (R >= 4) if (i == 2) { apply_pair_to<T, R, 2>(sr, si, dr, di, g); return; }
+    if constexpr (R >= 5) if (i == 3) { apply_pair_to<T, R, 3>(sr, si, dr, di, g); return; }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void apply_op(T (&vr)[1 << R], T (&vi)[1 << R], int i, const T* __restrict__ G) {
     if constexpr (R >= 2) if (i == 0) { apply_pair<T, R, 0>(vr, vi, G); return; }
@@ -296,6 +335,68 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
         for (int g = 0; g < pd.ngroups; ++g) {
             const int u0 = pd.u0[g];
             const int nops = pd.nops[g];
+#if FL_SWEEP_PINGPONG
+            // two register copies of the group: gates alternate A -> B -> A ...
+            T vr[SUB][1 << R], vi[SUB][1 << R], wr[SUB][1 << R], wi[SUB][1 << R];
+            uint32_t b0[SUB];
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+                b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
+#pragma unroll
+                for (int m = 0; m < (1 << R); ++m) {
+                    const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
+                    vr[s][m] = a.x;
+                    vi[s][m] = a.y;
+                }
+            }
+            T gc[32];
+            {
+                const T* G = gates + 32 * pd.opg[g][0];
+#pragma unroll
+                for (int k = 0; k < 32; ++k) gc[k] = G[k];
+            }
+            for (int q = 0; q < nops; q += 2) {
+                T gn[32];
+                {
+                    const int q1 = (q + 1 < nops) ? q + 1 : q;
+                    const T* G = gates + 32 * pd.opg[g][q1];
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) gn[k] = G[k];
+                }
+                const int i0 = pd.opi[g][q];
+#pragma unroll
+                for (int s = 0; s < SUB; ++s) apply_op_to<T, R>(vr[s], vi[s], wr[s], wi[s], i0, gc);
+                if (q + 1 < nops) {
+                    {
+                        const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
+                        const T* G = gates + 32 * pd.opg[g][q2];
+#pragma unroll
+                        for (int k = 0; k < 32; ++k) gc[k] = G[k];
+                    }
+                    const int i1 = pd.opi[g][q + 1];
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s) apply_op_to<T, R>(wr[s], wi[s], vr[s], vi[s], i1, gn);
+                } else {
+#pragma unroll
+                    for (int s = 0; s < SUB; ++s)
+#pragma unroll
+                        for (int m = 0; m < (1 << R); ++m) {
+                            vr[s][m] = wr[s][m];
+                            vi[s][m] = wi[s][m];
+                        }
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) {
+#pragma unroll
+                for (int m = 0; m < (1 << R); ++m) {
+                    cplx a;
+                    a.x = vr[s][m];
+                    a.y = vi[s][m];
+                    lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
+                }
+            }
+#else
             T vr[SUB][1 << R], vi[SUB][1 << R];
             uint32_t b0[SUB];
 #pragma unroll
@@ -347,6 +448,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
                     lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
                 }
             }
+#endif
             __syncthreads();
         }
         cplx* dst = psi + fl_tile_base(tile, C, W, h) + toff;
