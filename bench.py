@@ -73,6 +73,22 @@ def plan_passes(fl, L, n):
     return int(fl.fl_plan_query(L, "c64", 0, n, False)[3])
 
 
+def _dense_groups(fl, L, n):
+    """Register groups (= windows) of each pass of the dense plan for n periods."""
+    words = [int(x) for x in fl.fl_plan_query(L, "c64", 4, n, False)]
+    npasses, i, out = words[3], 4, []
+    for _ in range(npasses):
+        ng = words[i + 1]
+        i += 3
+        groups = []
+        for _ in range(ng):
+            nops = words[i + 1]
+            groups.append(words[i])
+            i += 2 + 3 * nops
+        out.append(groups)
+    return out
+
+
 def cpu_baseline(L, nsample):
     """The oracle as it stands, timed on a bounded sample: nsample gate
     applications spread over the chain at full size L, scaled to periods/s."""
@@ -206,6 +222,27 @@ def main():
         "energy_density_last": e_series[-1],
         "roofline": roof,
     }
+    # ---- the same step through the dense 6-qubit windows on the matrix cores
+    variants = {}
+    for var in ("dense6_fp32", "dense6_bf16x3"):
+        ev = fl.FloquetEngine(L, "c64", var)
+        ev.set_xyz(w["J"], w["fields"], w["T"])
+        ev.init(psi, w["spinors"])
+        ev.step(psi, nblk)
+        ev0.record(stream)
+        for _ in range(reps):
+            ev.step(psi, nblk)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / (nblk * reps)
+        nwin = sum(len(g) for g in _dense_groups(fl, L, nblk)) * reps
+        mflop = (512.0 if var == "dense6_fp32" else 1536.0) * (1 << L) * nwin / (ev0.elapsed_time(ev1) / 1e3) / 1e12
+        variants[var] = {"ms_per_period": round(ms, 3), "periods_per_s": round(1e3 / ms, 2),
+                         "windows_per_period": nwin / (nblk * reps), "mfma_tflops": round(mflop, 2),
+                         "mfma_peak": 157.3 if var == "dense6_fp32" else 2516.6,
+                         "energy_density_after_" + str(nblk * (reps + 1)): ev.energy_density(psi)}
+        del ev
+    out["dense_variants"] = variants
     del psi
     torch.cuda.empty_cache()
     if not args.no_adjoint:

@@ -168,9 +168,17 @@ int fl_xyz_generators(int L, double *gens_out);
  * Returns FL_EINVAL for L > 24 or an invalid window. */
 int fl_tile_map(int L, int dtype, int h, uint64_t *out);
 
+/* The 64x64 window matrix a dense plan applies for one register group:
+ * U = E(op_{n-1}) ... E(op_0), E(op_k) = the 4x4 gate G[k] ([nops][4][4]
+ * complex) embedded at window bits (pos[k], pos[k]+1), window index bit i =
+ * tile bit u0 + i, gate local index 2*bit(pos+1) + bit(pos).  U_out:
+ * [64][64] complex.  If frag_out is not NULL it receives the 64 KiB of MFMA
+ * fragments of the real 128x128 form for mode 0 (FP32) or 1 (bf16 hi/lo). */
+int fl_host_window_matrix(const double *G, const int *pos, int nops, int mode, double *U_out, void *frag_out);
+
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
  * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover,
- * 3 = cover used for H0 psi), flattened as int32:
+ * 3 = cover used for H0 psi, 4 = dense 6-qubit-window sweep), flattened as int32:
  * [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {i, gate, slot}*}*}*].
  * Writes at most cap words to buf (may be NULL) and the required count to
  * *needed. */

@@ -26,7 +26,7 @@ __all__ = [
     "fl_create", "fl_destroy", "fl_set_bonds", "fl_set_gates", "fl_init_state", "fl_apply_period",
     "fl_expect_energy", "fl_energy_spread", "fl_overlap", "fl_grad_workspace_bytes", "fl_grad",
     "fl_last_error", "fl_xyz_bonds", "fl_xyz_generators", "fl_host_gates", "fl_host_gate_derivative",
-    "fl_plan_query", "fl_tile_map", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
+    "fl_plan_query", "fl_tile_map", "fl_host_window_matrix", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
 ]
 
 _DTYPES = {"c64": FL_C64, "c128": FL_C128}
@@ -219,6 +219,21 @@ def fl_host_gate_derivative(h, gen, T: float) -> np.ndarray:
     out = np.zeros((4, 4), dtype=np.complex128)
     check(lib().fl_host_gate_derivative(_dp(hb), _dp(gb), float(T), _dp(out.view(np.float64))))
     return out
+
+
+def fl_host_window_matrix(G, pos, mode=None):
+    """(U, fragments) of a dense window: U = E(op_n-1)...E(op_0) (64x64) and, for
+    mode 0/1, the 64 KiB of MFMA fragments as raw bytes."""
+    G = np.asarray(G, dtype=np.complex128)
+    n = G.shape[0]
+    Gb = _c16(G, (n, 4, 4))
+    p = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
+    U = np.zeros((64, 64), dtype=np.complex128)
+    frag = np.zeros(65536, dtype=np.uint8) if mode is not None else None
+    check(lib().fl_host_window_matrix(_dp(Gb), p.ctypes.data_as(C.POINTER(C.c_int)), n,
+                                      -1 if mode is None else int(mode), _dp(U.view(np.float64)),
+                                      frag.ctypes.data_as(C.c_void_p) if frag is not None else None))
+    return U, frag
 
 
 def fl_plan_query(L: int, dtype="c64", kind: int = 0, n: int = 1, dagger: bool = False) -> np.ndarray:

@@ -42,6 +42,7 @@ SIGNATURES = {
     "fl_host_gate_derivative": (C.c_int, [dp, dp, C.c_double, dp]),
     "fl_xyz_generators": (C.c_int, [C.c_int, dp]),
     "fl_tile_map": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_uint64)]),
+    "fl_host_window_matrix": (C.c_int, [dp, C.POINTER(C.c_int), C.c_int, C.c_int, dp, vp]),
     "fl_plan_query": (C.c_int, [C.c_int, C.c_int, C.c_int, i64, C.c_int, C.POINTER(C.c_int32), i64,
                                 C.POINTER(i64)]),
 }

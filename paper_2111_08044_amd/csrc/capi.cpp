@@ -68,6 +68,11 @@ struct fl_ctx {
     double* d_mpart = nullptr; // gradient partials [kAdjGrid][L-1][16]
     std::map<std::pair<int, int>, std::vector<fl_pass>> plans;
     std::map<int, std::vector<fl_pass>> adj_plans;
+    struct DensePlan {
+        std::vector<fl_pass> passes;   // opg[g][0] = window matrix index
+        void* d_mats = nullptr;        // 64 KiB of MFMA fragments per window
+    };
+    std::map<std::pair<int, int>, DensePlan> dense_plans;
     std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
     std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
 };
@@ -138,6 +143,9 @@ int upload_mats(fl_ctx* c, void* dst, const std::vector<cd>& m, size_t nmat) {
 
 int install_gates(fl_ctx* c) {
     const int nb = c->L - 1;
+    for (auto& kv : c->dense_plans)
+        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
+    c->dense_plans.clear();
     std::vector<cd> both((size_t)2 * nb * 16);
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 4; ++i)
@@ -177,7 +185,86 @@ int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
     return FL_OK;
 }
 
+bool is_dense(const fl_ctx* c) { return c->variant == FL_DENSE6_FP32 || c->variant == FL_DENSE6_BF16X3; }
+
+// Fuse every register group of a 6-bit-window plan into its 64x64 matrix
+// (FP64 product of the embedded gates) and upload the MFMA fragments.
+int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
+    auto key = std::make_pair(n, dagger ? 1 : 0);
+    auto it = c->dense_plans.find(key);
+    if (it != c->dense_plans.end()) {
+        *out = &it->second;
+        return FL_OK;
+    }
+    const int nb = c->L - 1;
+    std::vector<fl_pass> plan = fl::plan_sweep(c->geom, n, dagger, false, kMaxGatesPerPass);
+    size_t nwin = 0;
+    for (const fl_pass& p : plan) nwin += p.ngroups;
+    const int mode = c->variant == FL_DENSE6_FP32 ? 0 : 1;
+    std::vector<unsigned char> frags(nwin * 65536);
+    std::vector<cd> U(64 * 64);
+    std::vector<cd> Gd((size_t)nb * 16);
+    for (int b = 0; b < nb; ++b)
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) Gd[(size_t)b * 16 + 4 * i + j] = std::conj(c->G[(size_t)b * 16 + 4 * j + i]);
+    size_t w = 0;
+    for (fl_pass& p : plan) {
+        for (int g = 0; g < p.ngroups; ++g) {
+            const cd* gates[FL_MAX_OPS];
+            int pos[FL_MAX_OPS];
+            for (int k = 0; k < p.nops[g]; ++k) {
+                const int gi = p.opg[g][k];
+                gates[k] = gi < nb ? &c->G[(size_t)gi * 16] : &Gd[(size_t)(gi - nb) * 16];
+                pos[k] = p.opi[g][k];
+            }
+            fl::window_matrix(gates, pos, p.nops[g], U.data());
+            fl::window_fragments(U.data(), mode, frags.data() + w * 65536);
+            p.nops[g] = 1;
+            p.opi[g][0] = 0;
+            p.opg[g][0] = (int16_t)w;
+            ++w;
+        }
+    }
+    fl_ctx::DensePlan dp;
+    dp.passes = plan;
+    if (nwin) {
+        hipError_t e = hipMalloc(&dp.d_mats, frags.size());
+        if (e != hipSuccess) return fail(FL_ENOMEM, "window matrices: device allocation failed");
+        e = hipMemcpy(dp.d_mats, frags.data(), frags.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(dp.d_mats);
+            return fail_hip(e, "window matrices upload");
+        }
+    }
+    auto& slot = c->dense_plans[key];
+    slot = dp;
+    *out = &slot;
+    return FL_OK;
+}
+
+int run_dense(fl_ctx* c, void* psi, int64_t n, bool dagger) {
+    const int mode = c->variant == FL_DENSE6_FP32 ? 0 : 1;
+    const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+    auto go = [&](int m) -> int {
+        fl_ctx::DensePlan* dp = nullptr;
+        int rc = build_dense_plan(c, m, dagger, &dp);
+        if (rc) return rc;
+        for (const fl_pass& p : dp->passes) {
+            hipError_t e = fl::launch_dense6(mode, c->geom, psi, dp->d_mats, p, c->stream);
+            if (e != hipSuccess) return fail_hip(e, "k_dense6 launch");
+        }
+        return FL_OK;
+    };
+    for (int64_t i = 0; i < q; ++i) {
+        int rc = go(kPlanBlock);
+        if (rc) return rc;
+    }
+    if (r > 0) return go((int)r);
+    return FL_OK;
+}
+
 int run_periods(fl_ctx* c, void* psi, int64_t n, bool dagger) {
+    if (is_dense(c)) return run_dense(c, psi, n, dagger);
     const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
     if (q > 0) {
         const auto& pb = get_plan(c, kPlanBlock, dagger);
@@ -238,7 +325,10 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "dtype must be FL_C64 or FL_C128");
     const int lmax = dtype == FL_C64 ? 34 : 33;
     if (L < 2 || L > lmax) return fail(FL_EINVAL, "L out of range [2, " + std::to_string(lmax) + "]");
-    if (variant != FL_PLAIN) return fail(FL_EINVAL, "variant not available in this build");
+    if (variant != FL_PLAIN && variant != FL_DENSE6_FP32 && variant != FL_DENSE6_BF16X3)
+        return fail(FL_EINVAL, "unknown variant");
+    if (variant != FL_PLAIN && (dtype != FL_C64 || L < 11))
+        return fail(FL_EINVAL, "dense 6-qubit windows need complex64 and L >= 11");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
         (void)hipGetLastError();
@@ -256,7 +346,8 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->variant = variant;
     c->dev = dev;
     c->stream = (hipStream_t)hip_stream;
-    c->geom = fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4);
+    c->geom = (variant == FL_PLAIN) ? fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4)
+                                    : fl::make_geom(L, FL_KMAX_C64, 6);
     c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4);
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
@@ -289,6 +380,8 @@ int fl_destroy(fl_ctx* c) {
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->d_tabs) (void)hipFree(c->d_tabs);
     if (c->d_mpart) (void)hipFree(c->d_mpart);
+    for (auto& kv : c->dense_plans)
+        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
     delete c;
     return FL_OK;
 }
@@ -633,6 +726,28 @@ int fl_tile_map(int L, int dtype, int h, uint64_t* out) {
     return FL_OK;
 }
 
+int fl_host_window_matrix(const double* G, const int* pos, int nops, int mode, double* U_out, void* frag_out) {
+    if (!G || !pos || nops < 0 || nops > 64 || !U_out) return fail(FL_EINVAL, "bad argument");
+    std::vector<cd> g((size_t)nops * 16);
+    std::vector<const cd*> gp(nops);
+    for (int k = 0; k < nops; ++k) {
+        if (pos[k] < 0 || pos[k] > 4) return fail(FL_EINVAL, "gate position out of the 6-bit window");
+        read_c16(G + (size_t)k * 32, &g[(size_t)k * 16]);
+        gp[k] = &g[(size_t)k * 16];
+    }
+    std::vector<cd> U(64 * 64);
+    fl::window_matrix(gp.data(), pos, nops, U.data());
+    for (int i = 0; i < 64 * 64; ++i) {
+        U_out[2 * i] = U[i].real();
+        U_out[2 * i + 1] = U[i].imag();
+    }
+    if (frag_out) {
+        if (mode != 0 && mode != 1) return fail(FL_EINVAL, "mode must be 0 or 1");
+        fl::window_fragments(U.data(), mode, frag_out);
+    }
+    return FL_OK;
+}
+
 int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* buf, int64_t cap, int64_t* needed) {
     if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "bad dtype");
     if (L < 2 || L > (dtype == FL_C64 ? 34 : 33)) return fail(FL_EINVAL, "L out of range");
@@ -659,11 +774,20 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     } else if (kind == 2) {
         g = fl::make_geom(L, FL_KMAX_RDM, 2);
         plan = fl::plan_cover(g);
+    } else if (kind == 4) {
+        if (dtype != FL_C64 || L < 11) return fail(FL_EINVAL, "dense plans need complex64 and L >= 11");
+        g = fl::make_geom(L, FL_KMAX_C64, 6);
+        const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
+        std::vector<fl_pass> pb, pr;
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass);
+        for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
+        plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 3) {
         g = fl::make_geom(L, kmax_of(dtype), 4);
         plan = fl::plan_cover(g);
     } else {
-        return fail(FL_EINVAL, "kind must be 0, 1, 2 or 3");
+        return fail(FL_EINVAL, "kind must be 0..4");
     }
     std::vector<int> words;
     fl::serialize_plan(g, plan, words);

@@ -15,6 +15,7 @@
 #include "host_math.h"
 
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 
 namespace fl {
@@ -181,6 +182,61 @@ void embed_gate(const cd* G, int nbits, int i, cd* U) {
             const int wr = rest | (row_l << i);
             U[(size_t)wr * n + w] += G[4 * row_l + col_l];
         }
+    }
+}
+
+void window_matrix(const cd* const* gates, const int* pos, int nops, cd* U) {
+    const int n = 64;
+    std::vector<cd> E((size_t)n * n);
+    for (int r = 0; r < n * n; ++r) U[r] = (r % (n + 1) == 0) ? cd(1.0) : cd(0.0);
+    for (int k = 0; k < nops; ++k) {
+        embed_gate(gates[k], 6, pos[k], E.data());
+        mat_mul_n(E.data(), U, U, n);
+    }
+}
+
+double bf16_rne(double a) {
+    if (a == 0.0 || !std::isfinite(a)) return a;
+    int e = 0;
+    std::frexp(a, &e);                        // a = f 2^e, 0.5 <= |f| < 1
+    const double scale = std::ldexp(1.0, e - 8);   // 8 significant bits
+    return std::nearbyint(a / scale) * scale;      // ties to even (default rounding mode)
+}
+
+static uint16_t bf16_bits(double v) {
+    const float f = (float)v;  // exact: v has at most 8 significant bits
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)(u >> 16);
+}
+
+void window_fragments(const cd* U, int mode, void* out) {
+    auto A = [&](int r, int k) -> double {
+        const int mr = r >> 1, cr = r & 1, mk = k >> 1, ck = k & 1;
+        const cd u = U[mr * 64 + mk];
+        if (cr == 0) return ck == 0 ? u.real() : -u.imag();
+        return ck == 0 ? u.imag() : u.real();
+    };
+    if (mode == 0) {
+        float* o = static_cast<float*>(out);
+        for (int w = 0; w < 4; ++w)
+            for (int l = 0; l < 64; ++l)
+                for (int kk = 0; kk < 64; ++kk)
+                    o[(w * 64 + l) * 64 + kk] = (float)A(32 * w + (l & 31), 2 * kk + (l >> 5));
+    } else {
+        uint16_t* hi = static_cast<uint16_t*>(out);
+        uint16_t* lo = hi + 16384;
+        for (int w = 0; w < 4; ++w)
+            for (int l = 0; l < 64; ++l)
+                for (int st = 0; st < 8; ++st)
+                    for (int i = 0; i < 8; ++i) {
+                        const double a = A(32 * w + (l & 31), 16 * st + 8 * (l >> 5) + i);
+                        const double h = bf16_rne(a);
+                        const double lw = bf16_rne(a - h);
+                        const size_t idx = (size_t)((w * 64 + l) * 8 + st) * 8 + i;
+                        hi[idx] = bf16_bits(h);
+                        lo[idx] = bf16_bits(lw);
+                    }
     }
 }
 

@@ -25,6 +25,20 @@ void mat_mul_n(const std::complex<double>* A, const std::complex<double>* B,
 // Embed a 4x4 gate on bits (i, i+1) of an nbits-bit window into a 2^nbits matrix.
 void embed_gate(const std::complex<double>* G, int nbits, int i, std::complex<double>* U);
 
+// U = E(op_{n-1}) ... E(op_0) on a 6-bit window, E = gate gates[k] embedded at
+// window bits (pos[k], pos[k]+1).  U: 64x64 row-major.
+void window_matrix(const std::complex<double>* const* gates, const int* pos, int nops, std::complex<double>* U);
+
+// Round-to-nearest-even to bfloat16 (8 significant bits), returned as a double.
+double bf16_rne(double a);
+
+// Per-lane MFMA fragments of the real 128x128 form of a 64x64 complex window
+// matrix (rows/columns ordered k = 2m + (0 re, 1 im)).  mode 0: 16384 floats,
+// [wave][lane][kk] = A[32 wave + lane%32][2 kk + lane/32].  mode 1: 16384
+// uint16 bf16 hi then 16384 lo, [wave][lane][step][i] =
+// A[32 wave + lane%32][16 step + 8 (lane/32) + i].  out: 64 KiB.
+void window_fragments(const std::complex<double>* U, int mode, void* out);
+
 // Factor tables of a product state psi[x] = thi[x >> (a+b)] tmid[(x >> a) & (2^b-1)] tlo[x & (2^a-1)].
 void product_tables(int L, const std::complex<double>* spinors, int a, int b,
                     std::vector<std::complex<double>>& tlo, std::vector<std::complex<double>>& tmid,

@@ -939,6 +939,162 @@ __global__ void k_zero(double* __restrict__ p, uint64_t n) {
 }
 
 // ---------------------------------------------------------------------------
+// dense 6-qubit windows on the matrix cores (complex64 states)
+// ---------------------------------------------------------------------------
+// Every register group of a dense plan is one window of 6 consecutive tile
+// bits [u0, u0+6); its gates were multiplied on the host (FP64) into a 64x64
+// complex matrix U, applied here as the real 128x128 contraction
+//   Y = A X,  A[2m'+c'][2m+c] = (Re U, -Im U; Im U, Re U)[c'][c] at (m', m),
+// on the 128-column matrix X whose column v is the 64-vector of amplitudes
+// sharing the other 7 tile bits, real index k = 2m + (0: re, 1: im).
+// Wave w owns output rows [32w, 32w+32) and keeps its A rows in VGPRs.
+//   MODE 0: FP32 MFMA v_mfma_f32_32x32x2f32 (k = 2 per step).
+//   MODE 1: split BF16x3: X = Xh + Xl, A = Ah + Al (round-to-nearest-even
+//           bf16 splits), Y = Ah Xh + Ah Xl + Al Xh with
+//           v_mfma_f32_32x32x16_bf16 and FP32 accumulation.
+// A fragments arrive pre-arranged per (wave, lane): MODE 0 as 64 floats
+// (step kk = k/2), MODE 1 as 8 steps x 8 bf16 for hi, then the same for lo.
+
+typedef float fl_f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 fl_bf16x8 __attribute__((ext_vector_type(8)));
+
+#define FL_DENSE_PLANE_STRIDE 136   // bf16 per column of a split plane (128 + 8 pad)
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense6(float2* __restrict__ psi, const float4* __restrict__ mats,
+                                                uint32_t ntiles, int C, int W, fl_pass pd) {
+    constexpr int KMAXD = 13;
+    constexpr int TILE_BYTES = (1 << KMAXD) * 8;
+    constexpr int PLANE_BYTES = 128 * FL_DENSE_PLANE_STRIDE * 2;
+    constexpr int LDS_BYTES = (MODE == 1 && 2 * PLANE_BYTES > TILE_BYTES) ? 2 * PLANE_BYTES : TILE_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    float2* lds = reinterpret_cast<float2*>(smem);
+    const int K = C + W;
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lc = lane & 31, lk = lane >> 5;
+    const int ncb = 1 << (K - 6 - 5);          // 32-column blocks (1, 2 or 4)
+    const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
+    tile_load<float, 0>(psi, base, K, C, h, lds);
+    __syncthreads();
+    for (int g = 0; g < pd.ngroups; ++g) {
+        const int u0 = pd.u0[g];
+        // 4096 float4 (64 KiB) per window; MODE 1 keeps hi at [0, 2048), lo at [2048, 4096)
+        const float4* M = mats + (size_t)pd.opg[g][0] * 4096 + (size_t)(w * 64 + lane) * (MODE == 0 ? 16 : 8);
+        uint32_t cbase[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) cbase[cb] = fl_spread((32 * cb + lc) & ((1 << (K - 6)) - 1), u0, 6);
+        fl_f32x16 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
+        if constexpr (MODE == 0) {
+            float a[64];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const float4 t = M[q];
+                a[4 * q] = t.x;
+                a[4 * q + 1] = t.y;
+                a[4 * q + 2] = t.z;
+                a[4 * q + 3] = t.w;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 64; ++kk) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb < ncb) {
+                        const float2 v = lds[fl_swz(cbase[cb] | ((uint32_t)kk << u0))];
+                        const float b = lk ? v.y : v.x;
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], b, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        } else {
+            // split the tile once into hi / lo planes laid out [column][k]
+            // (every thread reads its amplitudes, the workgroup syncs, then
+            // the planes overwrite the FP32 tile in LDS)
+            constexpr int PER = (1 << KMAXD) / 256;
+            float2 mine[PER];
+            const int nper = (1 << K) / 256;
+            const uint32_t l0 = fl_swz(threadIdx.x);   // fl_swz(tid + 256 t) = l0 + 256 t
+#pragma unroll
+            for (int t = 0; t < PER; ++t)
+                if (t < nper) mine[t] = lds[l0 + 256 * t];
+            __syncthreads();
+            __bf16* ph = reinterpret_cast<__bf16*>(smem);
+            __bf16* pl = ph + 128 * FL_DENSE_PLANE_STRIDE;
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                if (t < nper) {
+                    const uint32_t j = threadIdx.x + 256 * t;
+                    const uint32_t m = (j >> u0) & 63;
+                    const uint32_t lo_bits = j & ((1u << u0) - 1);
+                    const uint32_t col = lo_bits | ((j >> (u0 + 6)) << u0);
+                    const float2 x = mine[t];
+                    const __bf16 hr = (__bf16)x.x, hi_ = (__bf16)x.y;
+                    const __bf16 lr = (__bf16)(x.x - (float)hr), li = (__bf16)(x.y - (float)hi_);
+                    const uint32_t o = col * FL_DENSE_PLANE_STRIDE + 2 * m;
+                    ph[o] = hr;
+                    ph[o + 1] = hi_;
+                    pl[o] = lr;
+                    pl[o + 1] = li;
+                }
+            }
+            // A fragments are loaded after the split so that the two never
+            // occupy registers at the same time
+            fl_bf16x8 ah[8], al[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const float4 th = M[q], tl = M[2048 + q];
+                ah[q] = *reinterpret_cast<const fl_bf16x8*>(&th);
+                al[q] = *reinterpret_cast<const fl_bf16x8*>(&tl);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int st = 0; st < 8; ++st) {
+                const int k0 = 16 * st + 8 * lk;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb < ncb) {
+                        const uint32_t col = 32 * cb + lc;
+                        const uint32_t o = col * FL_DENSE_PLANE_STRIDE + k0;
+                        const fl_bf16x8 bh = *reinterpret_cast<const fl_bf16x8*>(ph + o);
+                        const fl_bf16x8 bl = *reinterpret_cast<const fl_bf16x8*>(pl + o);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[st], bh, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[st], bl, acc[cb], 0, 0, 0);
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[st], bh, acc[cb], 0, 0, 0);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // write Y back to the FP32 tile: register r of block cb holds row
+        // 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column 32 cb + lc
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            if (cb < ncb) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row0 = 32 * w + 8 * q + 4 * lk;     // even: rows row0..row0+3 = 2 amplitudes
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const uint32_t m = (row0 >> 1) + p;
+                        float2 v;
+                        v.x = acc[cb][4 * q + 2 * p];
+                        v.y = acc[cb][4 * q + 2 * p + 1];
+                        lds[fl_swz(cbase[cb] | (m << u0))] = v;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    tile_store<float, 0>(psi, base, K, C, h, lds);
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 
@@ -1106,6 +1262,17 @@ hipError_t launch_zero(double* p, uint64_t n, hipStream_t s) {
     const uint64_t want = (n + 255) / 256;
     const unsigned grid = (unsigned)(want < 4096 ? (want ? want : 1) : 4096);
     hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense6(int mode, const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s) {
+    const uint32_t nt = ntiles_of(g);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_dense6<0>, dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C, g.W,
+                           pd);
+    else
+        hipLaunchKernelGGL(k_dense6<1>, dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C, g.W,
+                           pd);
     return hipGetLastError();
 }
 

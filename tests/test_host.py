@@ -192,3 +192,80 @@ def test_plan_statistics_L30():
     _, _, _, passes = pt.parse_plan(fl.fl_plan_query(30, "c64", 0, n, False))
     per_period = len(passes) / n
     assert per_period <= 4.0, per_period
+
+
+# ------------------------------------------------------------ dense windows
+
+def _real_form(U):
+    """Real 128x128 form with k = 2m + (0 re, 1 im): written out from the
+    definition (Re U, -Im U; Im U, Re U) per 2x2 block."""
+    A = np.zeros((128, 128))
+    A[0::2, 0::2] = U.real
+    A[0::2, 1::2] = -U.imag
+    A[1::2, 0::2] = U.imag
+    A[1::2, 1::2] = U.real
+    return A
+
+
+def _bf16_rne(x):
+    """Round float64 values to 8 significant bits, ties to even (numpy)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    nz = x != 0
+    m, e = np.frexp(x[nz])
+    out[nz] = np.ldexp(np.round(np.ldexp(m, 8)), e - 8)   # np.round: half to even
+    return out
+
+
+def _bits_to_f(b):
+    return (np.asarray(b, dtype=np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def test_window_matrix_is_the_product_of_embedded_gates():
+    rng = np.random.default_rng(5)
+    n = 7
+    G = np.array([np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+                  for _ in range(n)])
+    pos = [0, 2, 4, 1, 3, 0, 2]
+    U, _ = fl.fl_host_window_matrix(G, pos)
+    ref = np.eye(64, dtype=complex)
+    for g, p in zip(G, pos):
+        # window bit i = site 5 - i of a 6-site chain (MSB first): bits (p, p+1) = bond 4 - p
+        ref = O.embed_bond(6, 4 - p, g) @ ref
+    assert np.max(np.abs(U - ref)) < 1e-14
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_window_fragments_layout_and_split(mode):
+    rng = np.random.default_rng(6)
+    G = np.array([np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+                  for _ in range(5)])
+    U, frag = fl.fl_host_window_matrix(G, [0, 1, 2, 3, 4], mode)
+    A = _real_form(U)
+    w, l = np.meshgrid(np.arange(4), np.arange(64), indexing="ij")
+    if mode == 0:
+        f = frag.view(np.float32).reshape(4, 64, 64).astype(np.float64)
+        kk = np.arange(64)
+        ref = A[(32 * w + (l & 31))[..., None], (2 * kk[None, None, :] + (l >> 5)[..., None])]
+        assert np.array_equal(f, ref.astype(np.float32).astype(np.float64))
+    else:
+        h = _bits_to_f(frag[:32768].view(np.uint16)).reshape(4, 64, 8, 8)
+        lo = _bits_to_f(frag[32768:].view(np.uint16)).reshape(4, 64, 8, 8)
+        st, i = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
+        rows = (32 * w + (l & 31))[..., None, None]
+        cols = 16 * st[None, None] + 8 * (l >> 5)[..., None, None] + i[None, None]
+        a = A[rows, cols]
+        assert np.array_equal(h, _bf16_rne(a))
+        assert np.array_equal(lo, _bf16_rne(a - h))
+        assert np.max(np.abs(a - h - lo)) <= 2.0 ** -17 * np.max(np.abs(a))
+
+
+@pytest.mark.parametrize("L", [11, 12, 13, 16, 30, 34])
+@pytest.mark.parametrize("n", [1, 7, 16, 17])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dense_plan_is_the_brickwork_circuit(L, n, dagger):
+    words = fl.fl_plan_query(L, "c64", 4, n, dagger)
+    C, W, R, passes = pt.parse_plan(words)
+    assert R == 6
+    seq = pt.gate_sequence(L, words)
+    pt.check_trace_equivalent(L, [b for b, _, _ in seq], n, dagger)
