@@ -61,6 +61,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
+    ap.add_argument("--study", choices=["precision", "echo"], default=None,
+                    help="instead of the throughput benchmark: error versus depth of the precision "
+                         "variants against an FP64 GPU run (precision), or the echo overlap error (echo)")
+    ap.add_argument("--max-periods", type=int, default=10000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the state once (a plain device copy of known size, the reference "
                          "for scaling hardware byte counters)")
@@ -143,6 +147,84 @@ def adjoint_ratio(fl, torch, L=24, n=200, K=50):
     return res
 
 
+def _depths(nmax):
+    d, out = 1, []
+    while d <= nmax:
+        for m in (1, 2, 5):
+            if m * d <= nmax:
+                out.append(m * d)
+        d *= 10
+    return out
+
+
+def precision_study(fl, torch, L, nmax):
+    """Infidelity 1 - |<psi64|psi>|^2/(|psi64|^2 |psi|^2), energy-density error
+    |e - e64| and norm drift of the complex64 variants (plain FP32 sweep, FP32
+    MFMA windows, split-BF16x3 MFMA windows) against an FP64 GPU run, at
+    depths 1, 2, 5, 10, ... up to nmax periods (same gates, same start)."""
+    import floquet_inputs as fin
+    w = fin.xyz_workload(L)
+    h = fl.fl_xyz_bonds(L, w["J"], w["fields"])
+    ref = fl.FloquetEngine(L, "c128")
+    ref.set_bonds(h, w["T"])
+    p64 = ref.new_state()
+    ref.init(p64, w["spinors"])
+    engines, states = {}, {}
+    for var in ("plain", "dense6_fp32", "dense6_bf16x3"):
+        e = fl.FloquetEngine(L, "c64", var)
+        e.set_bonds(h, w["T"])
+        engines[var] = e
+        states[var] = e.new_state()
+        e.init(states[var], w["spinors"])
+    rows, t, times = [], 0, {k: 0.0 for k in ["c128"] + list(engines)}
+    for d in _depths(nmax):
+        k = d - t
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ref.step(p64, k)
+        torch.cuda.synchronize()
+        times["c128"] += time.perf_counter() - t0
+        for var, e in engines.items():
+            t0 = time.perf_counter()
+            e.step(states[var], k)
+            torch.cuda.synchronize()
+            times[var] += time.perf_counter() - t0
+        t = d
+        E64, N64 = ref.energy(p64)
+        row = {"period": d, "e64": E64 / (L * N64), "norm64_minus_1": N64 - 1.0}
+        for var, e in engines.items():
+            ov, n64, n = ref.overlap(p64, states[var])
+            E, N = e.energy(states[var])
+            row[var] = {"infidelity": 1.0 - abs(ov) ** 2 / (n64 * n), "abs_e_err": abs(E / (L * N) - E64 / (L * N64)),
+                        "overlap_error": abs(1.0 - ov), "norm_minus_1": N - 1.0}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return {"study": "precision", "L": L, "periods": t, "rows": rows,
+            "ms_per_period": {k: round(v / t * 1e3, 3) for k, v in times.items()}}
+
+
+def echo_study(fl, torch, L, nmax):
+    """Echo of Sec. V: evolve d periods with U_F, then d with U_F^dagger, and
+    report |1 - <psi0|psi'0>| and the infidelity, complex64 plain sweep."""
+    import floquet_inputs as fin
+    w = fin.xyz_workload(L)
+    e = fl.FloquetEngine(L, "c64")
+    e.set_xyz(w["J"], w["fields"], w["T"])
+    psi0, psi = e.new_state(), e.new_state()
+    e.init(psi0, w["spinors"])
+    rows = []
+    for d in _depths(nmax):
+        psi.copy_(psi0)
+        e.step(psi, d)
+        e.step(psi, d, dagger=True)
+        ov, n0, n1 = e.overlap(psi0, psi)
+        row = {"t_f_periods": d, "overlap_error": abs(1.0 - ov), "infidelity": 1.0 - abs(ov) ** 2 / (n0 * n1),
+               "norm_minus_1": n1 - 1.0}
+        rows.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+    return {"study": "echo", "L": L, "rows": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -157,6 +239,12 @@ def main():
 
     L, m = args.L, args.periods_per_step
     torch.cuda.set_device(0)
+    if args.study == "precision":
+        print(json.dumps(precision_study(fl, torch, L, args.max_periods)), flush=True)
+        return
+    if args.study == "echo":
+        print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
+        return
     w = fin.xyz_workload(L)
     eng = fl.FloquetEngine(L, "c64")
     eng.set_xyz(w["J"], w["fields"], w["T"])
