@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--periods-per-step", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
     ap.add_argument("--study", choices=["precision", "echo"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
@@ -225,6 +226,38 @@ def echo_study(fl, torch, L, nmax):
     return {"study": "echo", "L": L, "rows": rows}
 
 
+def l34_leg(fl, torch, periods=16):
+    """L = 34 complex64 (128 GiB) in place: periods/s of the plain sweep and
+    the energy density after the run."""
+    import floquet_inputs as fin
+    L = 34
+    w = fin.xyz_workload(L)
+    eng = fl.FloquetEngine(L, "c64")
+    eng.set_xyz(w["J"], w["fields"], w["T"])
+    psi = eng.new_state()
+    eng.init(psi, w["spinors"])
+    e0 = eng.energy_density(psi)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    ev0.record(stream)
+    eng.step(psi, periods)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / periods
+    t0 = time.perf_counter()
+    e1 = eng.energy_density(psi)
+    t_e = time.perf_counter() - t0
+    npass = plan_passes(fl, L, 16) / 16
+    res = {"L": L, "state_gib": (1 << L) * 8 / 2**30, "periods": periods, "ms_per_period": round(ms, 2),
+           "periods_per_s": round(1e3 / ms, 3), "passes_per_period": npass,
+           "hbm_gbps": round(16.0 * (1 << L) * npass / (ms / 1e3) / 1e9, 1),
+           "sweep_tflops": round(32.0 * (L - 1) * (1 << L) / (ms / 1e3) / 1e12, 2),
+           "energy_readout_s": round(t_e, 3), "energy_density_0": e0, "energy_density_end": e1}
+    del psi, eng
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -335,6 +368,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(fl, torch)
+    if not args.no_l34:
+        out["l34"] = l34_leg(fl, torch)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, args.cpu_sample_gates)
     print(json.dumps(out), flush=True)

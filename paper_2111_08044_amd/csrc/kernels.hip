@@ -474,6 +474,51 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
 // other half with the partner lane, so the whole reduction costs
 // NV/2 + NV/4 + ... shuffles instead of NV * 6.  Written as a template
 // recursion so that every array index is a compile-time constant.
+// FP32 form on gfx950: the first two steps are one v_permlane32_swap /
+// v_permlane16_swap per value pair (the swap trades exactly the half that the
+// partner keeps, so x' + y' is the step's result without any select), the
+// distance-8 step moves the sent half by DPP row_ror:8 (= lane ^ 8 inside a
+// row of 16), and the final in-quad steps use DPP quad_perm.
+template <int CTRL>
+__device__ __forceinline__ float fl_dpp_f(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+template <int N, int D>
+__device__ __forceinline__ void tr_steps_f32(float (&v)[N], int lane) {
+    if constexpr (N > 1) {
+        constexpr int H = N / 2;
+#pragma unroll
+        for (int k = 0; k < H; ++k) {
+            if constexpr (D == 32 || D == 16) {
+                const auto r = (D == 32) ? __builtin_amdgcn_permlane32_swap(__float_as_uint(v[k]),
+                                                                            __float_as_uint(v[k + H]), false, false)
+                                         : __builtin_amdgcn_permlane16_swap(__float_as_uint(v[k]),
+                                                                            __float_as_uint(v[k + H]), false, false);
+                v[k] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+            } else {
+                const bool upper = (lane & D) != 0;
+                const float keep = upper ? v[k + H] : v[k];
+                const float send = upper ? v[k] : v[k + H];
+                float got;
+                if constexpr (D == 8)
+                    got = fl_dpp_f<0x128>(send);
+                else
+                    got = __shfl_xor(send, D);
+                v[k] = keep + got;
+            }
+        }
+        tr_steps_f32<H, D / 2>(*reinterpret_cast<float(*)[H]>(&v[0]), lane);
+    } else {
+        if constexpr (D >= 32) v[0] += __shfl_xor(v[0], 32);
+        if constexpr (D >= 16) v[0] += __shfl_xor(v[0], 16);
+        if constexpr (D >= 8) v[0] += fl_dpp_f<0x128>(v[0]);
+        if constexpr (D >= 4) v[0] += __shfl_xor(v[0], 4);
+        if constexpr (D >= 2) v[0] += fl_dpp_f<0x4E>(v[0]);   // quad_perm(2,3,0,1): lane ^ 2
+        if constexpr (D >= 1) v[0] += fl_dpp_f<0xB1>(v[0]);   // quad_perm(1,0,3,2): lane ^ 1
+    }
+}
+
 template <typename T, int N, int D>
 __device__ __forceinline__ void tr_steps(T (&v)[N], int lane) {
     if constexpr (N > 1) {
@@ -495,7 +540,10 @@ __device__ __forceinline__ void tr_steps(T (&v)[N], int lane) {
 template <typename T, int NV>
 __device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
     static_assert(NV >= 1 && NV <= 64 && (NV & (NV - 1)) == 0, "NV must be a power of two <= 64");
-    tr_steps<T, NV, 32>(v, threadIdx.x & 63);
+    if constexpr (sizeof(T) == 4)
+        tr_steps_f32<NV, 32>(v, threadIdx.x & 63);
+    else
+        tr_steps<T, NV, 32>(v, threadIdx.x & 63);
     return v[0];
 }
 
