@@ -42,17 +42,8 @@
 #ifndef FL_SWEEP_R_C64
 #define FL_SWEEP_R_C64 5     // register bits per group of the complex64 sweep
 #endif
-#ifndef FL_PERSIST_WG
-#define FL_PERSIST_WG 512    // workgroups of the persistent full-tile sweep (2 per CU)
-#endif
-#ifndef FL_SWEEP_PERSIST
-#define FL_SWEEP_PERSIST 0        // 1: FL_PERSIST_WG workgroups loop over the tiles
-#endif
-#ifndef FL_SWEEP_TILE_PREFETCH
-#define FL_SWEEP_TILE_PREFETCH 0  // 1: load the next tile into registers during the gates
-#endif
-#ifndef FL_SWEEP_PINGPONG
-#define FL_SWEEP_PINGPONG 0       // 1: gates alternate between two register copies (no moves)
+#ifndef FL_DIRECT_MIN_U0
+#define FL_DIRECT_MIN_U0 4   // lowest group bit for direct HBM <-> register transfers
 #endif
 #ifndef FL_SWEEP_GATE_PREFETCH
 #define FL_SWEEP_GATE_PREFETCH 1  // 1: fetch the next gate matrix during the current one

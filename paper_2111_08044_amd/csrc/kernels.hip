@@ -67,7 +67,13 @@ __device__ __forceinline__ void apply_pair(T (&vr)[1 << R], T (&vi)[1 << R], con
 }
 
 // Same, with the 16 complex gate entries already in registers (SGPRs: the
-// gate is uniform across the workgroup).
+// gate is uniform across the workgroup), updating the amplitudes in place.
+// Every output first sums the seven terms that do not hold its own input
+// amplitude; the last FMA of output (re|im)_i then adds the diagonal term
+// Re(G_ii) (re|im)_i.  That FMA is the last read of its input, so it can
+// write the result into the input's own register: each variant ends with
+// every amplitude in the register it started in, and the variants for
+// different I rejoin without register copies.
 // The empty asm markers carry the bit position as an immediate: they keep the
 // optimizer from merging the variants for different I into one body with
 // run-time register indices (which would force the arrays into scratch).
@@ -77,27 +83,27 @@ __device__ __forceinline__ void apply_pair_g(T (&vr)[1 << R], T (&vi)[1 << R], c
 #pragma unroll
     for (int c = 0; c < (1 << (R - 2)); ++c) {
         const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
-        T ar[4], ai[4];
+        T sr[4], si[4];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            ar[l] = vr[b | (l << I)];
-            ai[l] = vi[b | (l << I)];
+        for (int i = 0; i < 4; ++i) {
+            const int e = b | (i << I);
+            sr[i] = -g[8 * i + 2 * i + 1] * vi[e];
+            si[i] = g[8 * i + 2 * i + 1] * vr[e];
+#pragma unroll
+            for (int jj = 1; jj < 4; ++jj) {
+                const int j = (i + jj) & 3;
+                const int f = b | (j << I);
+                sr[i] = fma(g[8 * i + 2 * j], vr[f], sr[i]);
+                sr[i] = fma(-g[8 * i + 2 * j + 1], vi[f], sr[i]);
+                si[i] = fma(g[8 * i + 2 * j], vi[f], si[i]);
+                si[i] = fma(g[8 * i + 2 * j + 1], vr[f], si[i]);
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            T sr = g[8 * i] * ar[0];
-            T si = g[8 * i] * ai[0];
-            sr = fma(-g[8 * i + 1], ai[0], sr);
-            si = fma(g[8 * i + 1], ar[0], si);
-#pragma unroll
-            for (int j = 1; j < 4; ++j) {
-                sr = fma(g[8 * i + 2 * j], ar[j], sr);
-                sr = fma(-g[8 * i + 2 * j + 1], ai[j], sr);
-                si = fma(g[8 * i + 2 * j], ai[j], si);
-                si = fma(g[8 * i + 2 * j + 1], ar[j], si);
-            }
-            vr[b | (i << I)] = sr;
-            vi[b | (i << I)] = si;
+            const int e = b | (i << I);
+            vr[e] = fma(g[8 * i + 2 * i], vr[e], sr[i]);
+            vi[e] = fma(g[8 * i + 2 * i], vi[e], si[i]);
         }
     }
     __asm__ volatile("; end gate on register bits %0" ::"i"(I));
@@ -105,10 +111,12 @@ __device__ __forceinline__ void apply_pair_g(T (&vr)[1 << R], T (&vi)[1 << R], c
 
 template <typename T, int R>
 __device__ __forceinline__ void apply_op_g(T (&vr)[1 << R], T (&vi)[1 << R], int i, const T (&g)[32]) {
-    if constexpr (R >= 2) if (i == 0) { apply_pair_g<T, R, 0>(vr, vi, g); return; }
-    if constexpr (R >= 3) if (i == 1) { apply_pair_g<T, R, 1>(vr, vi, g); return; }
-    if constexpr (R >= 4) if (i == 2) { apply_pair_g<T, R, 2>(vr, vi, g); return; }
-    if constexpr (R >= 5) if (i == 3) { apply_pair_g<T, R, 3>(vr, vi, g); return; }
+    switch (i) {
+        case 0: if constexpr (R >= 2) apply_pair_g<T, R, 0>(vr, vi, g); break;
+        case 1: if constexpr (R >= 3) apply_pair_g<T, R, 1>(vr, vi, g); break;
+        case 2: if constexpr (R >= 4) apply_pair_g<T, R, 2>(vr, vi, g); break;
+        default: if constexpr (R >= 5) apply_pair_g<T, R, 3>(vr, vi, g); break;
+    }
 }
 
 // Out-of-place form: reads every amplitude of (sr, si) and writes the result
@@ -278,17 +286,35 @@ __global__ __launch_bounds__(FL_NT) void k_sweep(typename CT<T>::c* __restrict__
     tile_store<T, KT>(psi, base, K, C, h, lds);
 }
 
-// Full-size tiles (K = KT): persistent workgroups walk tiles
-// blockIdx.x, blockIdx.x + gridDim.x, ...; the next tile's global loads are
-// issued into registers before the current tile's gates run, so HBM latency
-// hides behind the gate arithmetic (a workgroup barrier on gfx950 waits for
-// LDS traffic only, not for outstanding global loads).  Every thread holds
-// SUB register groups of 2^R amplitudes and applies each gate to all of
-// them; the next gate's matrix is fetched while the current one is applied.
+// Op q of group g as (gate-table index, register bit), read as aligned 32-bit
+// words of the pass descriptor so that the loads stay scalar (sub-dword
+// loads of the kernel arguments would go through the vector memory path).
+typedef int32_t __attribute__((may_alias)) fl_i32a;
+__device__ __forceinline__ int pass_gate(const fl_pass& pd, int g, int q) {
+    const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.opg[g][0])[q >> 1];
+    return (q & 1) ? (w >> 16) : (int)(int16_t)(w & 0xffff);
+}
+__device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
+    const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.opi[g][0])[q >> 2];
+    return (w >> (8 * (q & 3))) & 0xff;
+}
+
+// lgkmcnt(0) with no wait on the vector-memory and export counters.
+#define FL_WAIT_LGKM0 0xc07f
+
+// Full-size tiles (K = KT), one tile per workgroup.  Every thread holds SUB
+// register groups of 2^R amplitudes and applies each gate to all of them; the
+// next gate's matrix is fetched while the current one is applied.
+//
+// The first group is loaded straight from HBM into its register layout, and
+// the last group stored straight back, when the group's lowest bit u0 is at
+// least FL_DIRECT_MIN_U0: the lanes then still cover runs of >= 2^4
+// contiguous amplitudes (>= 128 bytes), so every access coalesces.  This
+// saves one LDS round trip and one barrier at each end of the pass.  Groups
+// starting lower go through the LDS transpose, as every middle group does.
 template <typename T, int R, int KT, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_sweep_tiles(typename CT<T>::c* __restrict__ psi,
-                                                    const T* __restrict__ gates, uint32_t ntiles, int W,
-                                                    fl_pass pd) {
+                                                    const T* __restrict__ gates, int W, fl_pass pd) {
     typedef typename CT<T>::c cplx;
     constexpr int C = FL_LOWBITS;
     constexpr int K = KT;
@@ -299,6 +325,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type v16;
     __shared__ cplx lds[1 << K];
     const int h = pd.h;
+    const int ng = pd.ngroups;
+    cplx* const base = psi + fl_tile_base(blockIdx.x, C, W, h);
     // Element j = APL (tid + s NT) of a tile sits at toff + s * tstride: APL NT
     // is a multiple of 2^C, so s only moves the window part of the offset.
     static_assert((APL * NT) % (1 << C) == 0 && (APL * NT) % 256 == 0, "tile access stride");
@@ -307,19 +335,71 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     // LDS slot of element j + s APL NT is fl_swz(j) + s APL NT (the swizzle
     // only mixes bits 0..7), and fl_swz(j + 1) = fl_swz(j) ^ 1 for even j.
     const uint32_t l0 = fl_swz(APL * threadIdx.x);
-    v16 nxt[ITER];
-    uint32_t tile = blockIdx.x;
-    auto issue = [&](uint32_t t) {
-        const v16* src = reinterpret_cast<const v16*>(psi + fl_tile_base(t, C, W, h) + toff);
+    const bool din = ng > 0 && pd.u0[0] >= FL_DIRECT_MIN_U0;
+    const bool dout = ng > 0 && pd.u0[ng - 1] >= FL_DIRECT_MIN_U0;
+
+    T vr[SUB][1 << R], vi[SUB][1 << R];
+    uint32_t b0[SUB];
+    // HBM offsets of a register group: element b0 | (m << u0) of the tile sits
+    // at off(b0) + sum over the set bits k of m of d[k].
+    auto group_offsets = [&](int u0, uint64_t (&o)[SUB], uint64_t (&d)[R]) {
 #pragma unroll
-        for (int s = 0; s < ITER; ++s) nxt[s] = *reinterpret_cast<const v16*>(
-            reinterpret_cast<const typename CT<T>::c*>(src) + s * tstride);
+        for (int k = 0; k < R; ++k) {
+            const int q = u0 + k;
+            d[k] = q < C ? (1ull << q) : (1ull << (h + q - C));
+        }
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) {
+            b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
+            o[s] = fl_tile_offset(b0[s], C, h);
+        }
     };
-    if (FL_SWEEP_TILE_PREFETCH && tile < ntiles) issue(tile);
-    const uint32_t tile_step = FL_SWEEP_PERSIST ? gridDim.x : ntiles;
-    for (; tile < ntiles; tile += tile_step) {
-        if (!FL_SWEEP_TILE_PREFETCH) issue(tile);
-        __syncthreads();
+    auto moff = [&](const uint64_t (&d)[R], int m) {
+        uint64_t r = 0;
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            if ((m >> k) & 1) r += d[k];
+        return r;
+    };
+    auto lds_to_regs = [&](int u0) {
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) {
+            b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
+                vr[s][m] = a.x;
+                vi[s][m] = a.y;
+            }
+        }
+    };
+    auto regs_to_lds = [&](int u0) {
+#pragma unroll
+        for (int s = 0; s < SUB; ++s)
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                cplx a;
+                a.x = vr[s][m];
+                a.y = vi[s][m];
+                lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
+            }
+    };
+
+    if (din) {
+        uint64_t o[SUB], d[R];
+        group_offsets(pd.u0[0], o, d);
+#pragma unroll
+        for (int s = 0; s < SUB; ++s)
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                const cplx a = base[o[s] + moff(d, m)];
+                vr[s][m] = a.x;
+                vi[s][m] = a.y;
+            }
+    } else {
+        v16 nxt[ITER];
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) nxt[s] = *reinterpret_cast<const v16*>(base + toff + s * tstride);
 #pragma unroll
         for (int s = 0; s < ITER; ++s) {
             const uint32_t l = l0 + s * (APL * NT);
@@ -331,135 +411,77 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             }
         }
         __syncthreads();
-        if (FL_SWEEP_TILE_PREFETCH && tile + tile_step < ntiles) issue(tile + tile_step);
-        for (int g = 0; g < pd.ngroups; ++g) {
-            const int u0 = pd.u0[g];
-            const int nops = pd.nops[g];
-#if FL_SWEEP_PINGPONG
-            // two register copies of the group: gates alternate A -> B -> A ...
-            T vr[SUB][1 << R], vi[SUB][1 << R], wr[SUB][1 << R], wi[SUB][1 << R];
-            uint32_t b0[SUB];
+        if (ng > 0) lds_to_regs(pd.u0[0]);
+    }
+
+    for (int g = 0; g < ng; ++g) {
+        const int u0 = pd.u0[g];
+        const int nops = pd.nops[g];
+        if (g > 0) lds_to_regs(u0);
+        // Ops run two per iteration (the register copies that LLVM places on
+        // a loop back edge after the 4-way choice of gate bits are then not
+        // needed at all).  The next op's gate (32 scalar registers) is fetched
+        // while the current one is applied; an explicit lgkmcnt(0) before each
+        // fetch waits for the previous one, so that no wait inside an apply
+        // ever covers the fetch in flight.
+        T gc[32];
+        {
+            const T* G = gates + 32 * pass_gate(pd, g, 0);
 #pragma unroll
-            for (int s = 0; s < SUB; ++s) {
-                b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
-#pragma unroll
-                for (int m = 0; m < (1 << R); ++m) {
-                    const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
-                    vr[s][m] = a.x;
-                    vi[s][m] = a.y;
-                }
-            }
-            T gc[32];
-            {
-                const T* G = gates + 32 * pd.opg[g][0];
-#pragma unroll
-                for (int k = 0; k < 32; ++k) gc[k] = G[k];
-            }
-            for (int q = 0; q < nops; q += 2) {
-                T gn[32];
-                {
-                    const int q1 = (q + 1 < nops) ? q + 1 : q;
-                    const T* G = gates + 32 * pd.opg[g][q1];
-#pragma unroll
-                    for (int k = 0; k < 32; ++k) gn[k] = G[k];
-                }
-                const int i0 = pd.opi[g][q];
-#pragma unroll
-                for (int s = 0; s < SUB; ++s) apply_op_to<T, R>(vr[s], vi[s], wr[s], wi[s], i0, gc);
-                if (q + 1 < nops) {
-                    {
-                        const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
-                        const T* G = gates + 32 * pd.opg[g][q2];
-#pragma unroll
-                        for (int k = 0; k < 32; ++k) gc[k] = G[k];
-                    }
-                    const int i1 = pd.opi[g][q + 1];
-#pragma unroll
-                    for (int s = 0; s < SUB; ++s) apply_op_to<T, R>(wr[s], wi[s], vr[s], vi[s], i1, gn);
-                } else {
-#pragma unroll
-                    for (int s = 0; s < SUB; ++s)
-#pragma unroll
-                        for (int m = 0; m < (1 << R); ++m) {
-                            vr[s][m] = wr[s][m];
-                            vi[s][m] = wi[s][m];
-                        }
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < SUB; ++s) {
-#pragma unroll
-                for (int m = 0; m < (1 << R); ++m) {
-                    cplx a;
-                    a.x = vr[s][m];
-                    a.y = vi[s][m];
-                    lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
-                }
-            }
-#else
-            T vr[SUB][1 << R], vi[SUB][1 << R];
-            uint32_t b0[SUB];
-#pragma unroll
-            for (int s = 0; s < SUB; ++s) {
-                b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
-#pragma unroll
-                for (int m = 0; m < (1 << R); ++m) {
-                    const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
-                    vr[s][m] = a.x;
-                    vi[s][m] = a.y;
-                }
-            }
-            T gc[32];
-            {
-                const T* G = gates + 32 * pd.opg[g][0];
-#pragma unroll
-                for (int k = 0; k < 32; ++k) gc[k] = G[k];
-            }
-            for (int q = 0; q < nops; ++q) {
-                const int i = pd.opi[g][q];
-                if constexpr (sizeof(T) == 4 && FL_SWEEP_GATE_PREFETCH) {
-                    // prefetch the next gate (32 SGPRs) while this one is applied
-                    const int qn = (q + 1 < nops) ? q + 1 : q;
-                    const T* Gn = gates + 32 * pd.opg[g][qn];
-                    T gn[32];
-#pragma unroll
-                    for (int k = 0; k < 32; ++k) gn[k] = Gn[k];
-#pragma unroll
-                    for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
-#pragma unroll
-                    for (int k = 0; k < 32; ++k) gc[k] = gn[k];
-                } else {
-                    if (q > 0) {
-                        const T* G = gates + 32 * pd.opg[g][q];
-#pragma unroll
-                        for (int k = 0; k < 32; ++k) gc[k] = G[k];
-                    }
-#pragma unroll
-                    for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < SUB; ++s) {
-#pragma unroll
-                for (int m = 0; m < (1 << R); ++m) {
-                    cplx a;
-                    a.x = vr[s][m];
-                    a.y = vi[s][m];
-                    lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
-                }
-            }
-#endif
-            __syncthreads();
+            for (int k = 0; k < 32; ++k) gc[k] = G[k];
         }
-        cplx* dst = psi + fl_tile_base(tile, C, W, h) + toff;
+        int i = pass_bit(pd, g, 0);
+        for (int q = 0; q < nops; q += 2) {
+            __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+            const int q1 = (q + 1 < nops) ? q + 1 : q;
+            const int i1 = pass_bit(pd, g, q1);
+            T g1[32];
+            {
+                const T* G = gates + 32 * pass_gate(pd, g, q1);
+#pragma unroll
+                for (int k = 0; k < 32; ++k) g1[k] = G[k];
+            }
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
+            if (q + 1 < nops) {
+                __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+                const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
+                i = pass_bit(pd, g, q2);
+                {
+                    const T* G = gates + 32 * pass_gate(pd, g, q2);
+#pragma unroll
+                    for (int k = 0; k < 32; ++k) gc[k] = G[k];
+                }
+#pragma unroll
+                for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i1, g1);
+            }
+        }
+        if (g == ng - 1 && dout) break;
+        regs_to_lds(u0);
+        __syncthreads();
+    }
+
+    if (dout) {
+        uint64_t o[SUB], d[R];
+        group_offsets(pd.u0[ng - 1], o, d);
+#pragma unroll
+        for (int s = 0; s < SUB; ++s)
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                cplx a;
+                a.x = vr[s][m];
+                a.y = vi[s][m];
+                base[o[s] + moff(d, m)] = a;
+            }
+    } else {
 #pragma unroll
         for (int s = 0; s < ITER; ++s) {
             const uint32_t l = l0 + s * (APL * NT);
             if constexpr (sizeof(T) == 4) {
                 const float2 a = lds[l], b = lds[l ^ 1];
-                *reinterpret_cast<float4*>(dst + s * tstride) = make_float4(a.x, a.y, b.x, b.y);
+                *reinterpret_cast<float4*>(base + toff + s * tstride) = make_float4(a.x, a.y, b.x, b.y);
             } else {
-                *reinterpret_cast<v16*>(dst + s * tstride) = lds[l];
+                *reinterpret_cast<v16*>(base + toff + s * tstride) = lds[l];
             }
         }
     }
@@ -1155,10 +1177,8 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         float2* p = (float2*)psi;
         const float* G = (const float*)gates;
         if (g.K == FL_KMAX_C64 && g.W > 0) {
-            const uint32_t nt = ntiles_of(g);
-            const uint32_t pg = (FL_SWEEP_PERSIST && nt > FL_PERSIST_WG) ? FL_PERSIST_WG : nt;
-            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(pg),
-                               dim3(FL_SWEEP_NT_C64), 0, s, p, G, nt, g.W, pd);
+            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), grid,
+                               dim3(FL_SWEEP_NT_C64), 0, s, p, G, g.W, pd);
         } else if (g.R == 5)
             hipLaunchKernelGGL((k_sweep<float, 5, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 4)
@@ -1171,10 +1191,7 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         double2* p = (double2*)psi;
         const double* G = (const double*)gates;
         if (g.K == FL_KMAX_C128 && g.W > 0) {
-            const uint32_t nt = ntiles_of(g);
-            const uint32_t pg = (FL_SWEEP_PERSIST && nt > FL_PERSIST_WG) ? FL_PERSIST_WG : nt;
-            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256>), dim3(pg), dim3(256), 0, s, p, G, nt,
-                               g.W, pd);
+            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256>), grid, dim3(256), 0, s, p, G, g.W, pd);
         } else if (g.R == 4)
             hipLaunchKernelGGL((k_sweep<double, 4, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 3)
