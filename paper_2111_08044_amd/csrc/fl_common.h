@@ -19,6 +19,7 @@
 // amplitudes) while it applies the group's ops, each op a 4x4 gate on the
 // register bits (i, i+1), optionally preceded by a reduction into a slot.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #if defined(__HIPCC__)
@@ -61,6 +62,13 @@ struct fl_pass {
     int16_t opg[FL_MAX_GROUPS][FL_MAX_OPS];  // gate-table index, -1 = no gate
     int16_t ops[FL_MAX_GROUPS][FL_MAX_OPS];  // reduction slot (index into sbond), -1 = none
 };
+
+#ifdef __cplusplus
+// Kernels read the per-op arrays as aligned 32-bit words (scalar loads).
+static_assert(offsetof(fl_pass, opi) % 4 == 0 && sizeof(((fl_pass*)0)->opi[0]) % 4 == 0, "opi rows not word aligned");
+static_assert(offsetof(fl_pass, opg) % 4 == 0 && sizeof(((fl_pass*)0)->opg[0]) % 4 == 0, "opg rows not word aligned");
+static_assert(offsetof(fl_pass, ops) % 4 == 0 && sizeof(((fl_pass*)0)->ops[0]) % 4 == 0, "ops rows not word aligned");
+#endif
 
 struct fl_geom {
     int L, C, W, K, R;

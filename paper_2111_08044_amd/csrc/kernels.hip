@@ -109,14 +109,39 @@ __device__ __forceinline__ void apply_pair_g(T (&vr)[1 << R], T (&vi)[1 << R], c
     __asm__ volatile("; end gate on register bits %0" ::"i"(I));
 }
 
+// Calls f(std::integral_constant<int, I>) for the run-time bit position
+// i in [0, R-2].  The last position is the switch default, so every path of
+// the switch applies a gate: a path that did nothing would rejoin the others
+// with the untouched values and cost register copies at the join.
+template <int R, typename F>
+__device__ __forceinline__ void with_bit(int i, F&& f) {
+    static_assert(R >= 2 && R <= 5, "register group size");
+    if constexpr (R == 2) {
+        f(std::integral_constant<int, 0>{});
+    } else if constexpr (R == 3) {
+        switch (i) {
+            case 0: f(std::integral_constant<int, 0>{}); break;
+            default: f(std::integral_constant<int, 1>{}); break;
+        }
+    } else if constexpr (R == 4) {
+        switch (i) {
+            case 0: f(std::integral_constant<int, 0>{}); break;
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            default: f(std::integral_constant<int, 2>{}); break;
+        }
+    } else {
+        switch (i) {
+            case 0: f(std::integral_constant<int, 0>{}); break;
+            case 1: f(std::integral_constant<int, 1>{}); break;
+            case 2: f(std::integral_constant<int, 2>{}); break;
+            default: f(std::integral_constant<int, 3>{}); break;
+        }
+    }
+}
+
 template <typename T, int R>
 __device__ __forceinline__ void apply_op_g(T (&vr)[1 << R], T (&vi)[1 << R], int i, const T (&g)[32]) {
-    switch (i) {
-        case 0: if constexpr (R >= 2) apply_pair_g<T, R, 0>(vr, vi, g); break;
-        case 1: if constexpr (R >= 3) apply_pair_g<T, R, 1>(vr, vi, g); break;
-        case 2: if constexpr (R >= 4) apply_pair_g<T, R, 2>(vr, vi, g); break;
-        default: if constexpr (R >= 5) apply_pair_g<T, R, 3>(vr, vi, g); break;
-    }
+    with_bit<R>(i, [&](auto I) { apply_pair_g<T, R, decltype(I)::value>(vr, vi, g); });
 }
 
 // Out-of-place form: reads every amplitude of (sr, si) and writes the result
@@ -292,6 +317,10 @@ __global__ __launch_bounds__(FL_NT) void k_sweep(typename CT<T>::c* __restrict__
 typedef int32_t __attribute__((may_alias)) fl_i32a;
 __device__ __forceinline__ int pass_gate(const fl_pass& pd, int g, int q) {
     const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.opg[g][0])[q >> 1];
+    return (q & 1) ? (w >> 16) : (int)(int16_t)(w & 0xffff);
+}
+__device__ __forceinline__ int pass_slot(const fl_pass& pd, int g, int q) {
+    const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.ops[g][0])[q >> 1];
     return (q & 1) ? (w >> 16) : (int)(int16_t)(w & 0xffff);
 }
 __device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
@@ -880,45 +909,54 @@ __global__ __launch_bounds__(FL_NT) void k_apply_h(const typename CT<T>::c* __re
 // D_03, D_12, D_13, D_23.
 // Mpart layout: [gridDim.x][nbonds][16] doubles, accumulated across launches.
 
-template <typename T, int R>
+template <typename T, int R, int I>
 __device__ __forceinline__ void adj_overlap(const T (&pr)[1 << R], const T (&pi)[1 << R], const T (&lr)[1 << R],
-                                            const T (&li)[1 << R], int i, T (&d)[16]) {
+                                            const T (&li)[1 << R], T (&d)[16]) {
 #pragma unroll
-    for (int I = 0; I <= R - 2; ++I) {
-        if (I != i) continue;
+    for (int c = 0; c < (1 << (R - 2)); ++c) {
+        const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+        T ar[4], ai[4], br[4], bi[4];   // a = lambda, b = psi
 #pragma unroll
-        for (int c = 0; c < (1 << (R - 2)); ++c) {
-            const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
-            T ar[4], ai[4], br[4], bi[4];   // a = lambda, b = psi
-#pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                ar[l] = lr[b | (l << I)];
-                ai[l] = li[b | (l << I)];
-                br[l] = pr[b | (l << I)];
-                bi[l] = pi[b | (l << I)];
-            }
-#pragma unroll
-            for (int l = 0; l < 4; ++l) d[l] = fma(ar[l], bi[l], fma(-ai[l], br[l], d[l]));
-            int k = 4;
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = x + 1; y < 4; ++y) {
-                    T re = d[k], im = d[k + 1];
-                    re = fma(ar[x], br[y], re);
-                    re = fma(ai[x], bi[y], re);
-                    re = fma(-br[x], ar[y], re);
-                    re = fma(-bi[x], ai[y], re);
-                    im = fma(ar[x], bi[y], im);
-                    im = fma(-ai[x], br[y], im);
-                    im = fma(-br[x], ai[y], im);
-                    im = fma(bi[x], ar[y], im);
-                    d[k] = re;
-                    d[k + 1] = im;
-                    k += 2;
-                }
+        for (int l = 0; l < 4; ++l) {
+            ar[l] = lr[b | (l << I)];
+            ai[l] = li[b | (l << I)];
+            br[l] = pr[b | (l << I)];
+            bi[l] = pi[b | (l << I)];
         }
+#pragma unroll
+        for (int l = 0; l < 4; ++l) d[l] = fma(ar[l], bi[l], fma(-ai[l], br[l], d[l]));
+        int k = 4;
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = x + 1; y < 4; ++y) {
+                T re = d[k], im = d[k + 1];
+                re = fma(ar[x], br[y], re);
+                re = fma(ai[x], bi[y], re);
+                re = fma(-br[x], ar[y], re);
+                re = fma(-bi[x], ai[y], re);
+                im = fma(ar[x], bi[y], im);
+                im = fma(-ai[x], br[y], im);
+                im = fma(-br[x], ai[y], im);
+                im = fma(bi[x], ar[y], im);
+                d[k] = re;
+                d[k + 1] = im;
+                k += 2;
+            }
     }
+}
+
+// One reverse op on register bits (I, I+1): the overlap terms of the op's
+// slot (before the gate), then the gate on psi and on lambda.  Every op of a
+// reverse plan has both a slot and a gate (the host checks this), so the
+// variants hold no further branches.
+template <typename T, int R, int I>
+__device__ __forceinline__ void adj_op(T (&pr)[1 << R], T (&pi)[1 << R], T (&lr)[1 << R], T (&li)[1 << R],
+                                       const T (&g)[32], T (&d)[16]) {
+    __asm__ volatile("; adjoint op on register bits %0" ::"i"(I));
+    adj_overlap<T, R, I>(pr, pi, lr, li, d);
+    apply_pair_g<T, R, I>(pr, pi, g);
+    apply_pair_g<T, R, I>(lr, li, g);
 }
 
 template <typename T, int R, int KT, int KMAX>
@@ -957,21 +995,41 @@ __global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(2))) void
                 lr[m] = b.x;
                 li[m] = b.y;
             }
-            for (int q = 0; q < nops; ++q) {
-                const int i = pd.opi[g][q];
-                const int slot = pd.ops[g][q];
-                if (slot >= 0) {
-                    T d[16];
+            // Ops run two per iteration with the op metadata read as scalar
+            // words and the gate fetched into scalar registers one op ahead
+            // (the structure of the forward sweep's op loop).
+            auto fetch = [&](int q, int& i, int& slot, T (&gg)[32]) {
+                i = pass_bit(pd, g, q);
+                slot = pass_slot(pd, g, q);
+                const T* G = gates + 32 * pass_gate(pd, g, q);
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) d[k] = 0;
-                    adj_overlap<T, R>(pr, pi, lr, li, i, d);
-                    const T r = wave_transpose_reduce<T, 16>(d);
-                    if ((lane & 3) == 0) wacc[wave][slot][lane >> 2] += (double)r;
-                }
-                const int gi = pd.opg[g][q];
-                if (gi >= 0) {
-                    apply_op<T, R>(pr, pi, i, gates + 32 * gi);
-                    apply_op<T, R>(lr, li, i, gates + 32 * gi);
+                for (int k = 0; k < 32; ++k) gg[k] = G[k];
+            };
+            auto run = [&](int i, int slot, const T (&gg)[32]) {
+                T d[16];
+#pragma unroll
+                for (int k = 0; k < 16; ++k) d[k] = 0;
+                with_bit<R>(i, [&](auto I) { adj_op<T, R, decltype(I)::value>(pr, pi, lr, li, gg, d); });
+                // lane l holds the sum of value l >> 2; one lane of each
+                // four adds it and the other three add zero, as an LDS atomic
+                // with every lane active (no divergent branch in the op loop)
+                const T r = wave_transpose_reduce<T, 16>(d);
+                __hip_atomic_fetch_add(&wacc[wave][slot][lane >> 2], (lane & 3) == 0 ? (double)r : 0.0,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            int i0, s0;
+            T gc[32];
+            fetch(0, i0, s0, gc);
+            for (int q = 0; q < nops; q += 2) {
+                __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+                int i1, s1;
+                T gn[32];
+                fetch((q + 1 < nops) ? q + 1 : q, i1, s1, gn);
+                run(i0, s0, gc);
+                if (q + 1 < nops) {
+                    __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+                    fetch((q + 2 < nops) ? q + 2 : q + 1, i0, s0, gc);
+                    run(i1, s1, gn);
                 }
             }
             if (active) {
