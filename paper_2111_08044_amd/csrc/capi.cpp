@@ -75,6 +75,7 @@ struct fl_ctx {
     std::map<std::pair<int, int>, DensePlan> dense_plans;
     std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
     std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
+    std::vector<fl_win> cover_win;    // per cover_rdm pass: window-bond form (h < 0: not eligible)
 };
 
 namespace {
@@ -177,8 +178,11 @@ void rho_from16(const double* v, cd* rho) {
 
 int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
     const int grid = (int)std::min<uint32_t>(ntiles(c->geom_rdm), kReduceGrid);
-    for (const fl_pass& p : c->cover_rdm) {
-        hipError_t e = fl::launch_rdm(c->dtype, c->geom_rdm, psi, p, c->d_part, grid, c->L, c->stream);
+    for (size_t k = 0; k < c->cover_rdm.size(); ++k) {
+        const fl_win& w = c->cover_win[k];
+        hipError_t e = w.h >= 0 ? fl::launch_rdm_win(c->geom_rdm, psi, w, c->d_part, grid, c->L, c->stream)
+                                : fl::launch_rdm(c->dtype, c->geom_rdm, psi, c->cover_rdm[k], c->d_part, grid, c->L,
+                                                 c->stream);
         if (e != hipSuccess) return fail_hip(e, "k_rdm launch");
     }
     *grid_out = grid;
@@ -352,6 +356,23 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
     c->cover_rdm = fl::plan_cover(c->geom_rdm);
+    // complex64 passes whose bonds all lie inside the high window (no low-bit
+    // bond, no norm) run in the register-window reduction kernel
+    for (const fl_pass& p : c->cover_rdm) {
+        fl_win w;
+        w.h = -1;
+        for (int i = 0; i < 8; ++i) w.slot[i] = -1;
+        bool ok = dtype == FL_C64 && c->geom_rdm.W == FL_KMAX_RDM - FL_LOWBITS && c->geom_rdm.C == FL_LOWBITS &&
+                  p.flags == 0 && p.ngroups > 0;
+        for (int gi = 0; ok && gi < p.ngroups; ++gi) {
+            const int i = p.u0[gi] - FL_LOWBITS;
+            if (i < 0 || i + 1 >= c->geom_rdm.W || p.nops[gi] != 1) ok = false;
+            else w.slot[i] = p.ops[gi][0];
+        }
+        if (ok) w.h = p.h;
+        else for (int i = 0; i < 8; ++i) w.slot[i] = -1;
+        c->cover_win.push_back(w);
+    }
     const int nb = L - 1;
     const size_t rb = dtype == FL_C64 ? 4 : 8;
     hipError_t e = hipSuccess;

@@ -608,6 +608,25 @@ __device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
 #define FL_RDM_MAXG 16
 #define FL_RDM_TILE_MAXG 13   // bond slots of a full-tile cover pass (K-1 <= 12) + the norm
 
+// Adds one quad (amplitudes a_0..a_3 of a bond's local index) to the 16
+// density-matrix sums: [0..3] |a_l|^2, then for each pair l < m the real and
+// imaginary parts of conj(a_l) a_m (as ar_l ar_m + ai_l ai_m and
+// ai_l ar_m - ar_l ai_m), pairs in the order 01, 02, 03, 12, 13, 23.
+template <typename T>
+__device__ __forceinline__ void rdm_quad(const T (&ar)[4], const T (&ai)[4], T (&r)[16]) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) r[l] = fma(ar[l], ar[l], fma(ai[l], ai[l], r[l]));
+    int k = 4;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 4; ++j) {
+            r[k] = fma(ar[i], ar[j], fma(ai[i], ai[j], r[k]));
+            r[k + 1] = fma(ai[i], ar[j], fma(-ar[i], ai[j], r[k + 1]));
+            k += 2;
+        }
+}
+
 template <typename T, int KT, int KMAX>
 __global__ __launch_bounds__(FL_NT) void k_rdm(const typename CT<T>::c* __restrict__ psi, int C, int W,
                                                uint32_t ntiles, fl_pass pd, double* __restrict__ partials,
@@ -750,17 +769,7 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
                     ar[l] = a.x;
                     ai[l] = a.y;
                 }
-#pragma unroll
-                for (int l = 0; l < 4; ++l) r[l] = fma(ar[l], ar[l], fma(ai[l], ai[l], r[l]));
-                int k = 4;
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int j = i + 1; j < 4; ++j) {
-                        r[k] = fma(ar[i], ar[j], fma(ai[i], ai[j], r[k]));
-                        r[k + 1] = fma(ai[i], ar[j], fma(-ar[i], ai[j], r[k + 1]));
-                        k += 2;
-                    }
+                rdm_quad<T>(ar, ai, r);
             }
             const T red = wave_transpose_reduce<T, 16>(r);
             if ((lane & 3) == 0) wacc[wave][g][lane >> 2] += (double)red;
@@ -789,6 +798,88 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
 // ---------------------------------------------------------------------------
 // product state, overlap, finalize
 // ---------------------------------------------------------------------------
+
+// Window-bond reduction (complex64): for a cover pass whose bonds all lie in
+// the high window [h, h+WB), one wave takes one tile at a time with its 64
+// lanes on the C low bits (every load instruction reads 512 contiguous bytes)
+// and the 2^WB window amplitudes of each lane in registers, so the density
+// matrices of all WB-1 window bonds come straight from registers: no LDS
+// staging and no barrier.  Each lane sums its quads in FP32 for up to
+// kFlush tiles, then a wave transpose-reduction moves those sums into FP64
+// accumulators (lane l: value l >> 2 of each bond); the four waves of the
+// workgroup are summed at the end into partials[blockIdx][slot][16] for the
+// bonds the pass asks for (slot[i] >= 0 for window bit pair (i, i+1)).
+template <int WB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rdm_win(
+    const float2* __restrict__ psi, uint32_t ntiles, fl_win pw, double* __restrict__ partials, int nslot) {
+    constexpr int C = FL_LOWBITS;
+    constexpr int NB = WB - 1;
+    constexpr int M = 1 << WB;
+    constexpr int kFlush = 8;
+    static_assert(C == 6, "one lane per low-bit value");
+    __shared__ double wsum[4][NB][16];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int h = pw.h;
+    float r[NB][16];
+    double acc[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        acc[i] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) r[i][k] = 0.f;
+    }
+    auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            acc[i] += (double)wave_transpose_reduce<float, 16>(r[i]);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) r[i][k] = 0.f;
+        }
+    };
+    const uint32_t step = gridDim.x * 4u;
+    for (uint32_t t0 = blockIdx.x * 4u + (uint32_t)wave; t0 < ntiles; t0 += kFlush * step) {
+        const uint32_t tend = min(ntiles, t0 + kFlush * step);
+        for (uint32_t t = t0; t < tend; t += step) {
+            const float2* src = psi + fl_tile_base(t, C, WB, h) + lane;
+            // hide the stride from loop-invariant code motion: hoisting the 64
+            // offsets m << h out of the tile loop would take 128 SGPRs and spill
+            uint64_t stride = 1ull << h;
+            __asm__ volatile("" : "+s"(stride));
+            float vr[M], vi[M];
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const float2 a = src[m * stride];
+                vr[m] = a.x;
+                vi[m] = a.y;
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+#pragma unroll
+                for (int c = 0; c < M / 4; ++c) {
+                    const int b = (c & ((1 << i) - 1)) | ((c >> i) << (i + 2));
+                    float ar[4], ai[4];
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        ar[l] = vr[b | (l << i)];
+                        ai[l] = vi[b | (l << i)];
+                    }
+                    rdm_quad<float>(ar, ai, r[i]);
+                }
+        }
+        flush();
+    }
+    if ((lane & 3) == 0)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) wsum[wave][i][lane >> 2] = acc[i];
+    __syncthreads();
+    for (int t = threadIdx.x; t < NB * 16; t += 256) {
+        const int i = t >> 4, v = t & 15;
+        const int slot = pw.slot[i];
+        if (slot < 0) continue;
+        partials[((size_t)blockIdx.x * nslot + slot) * 16 + v] = wsum[0][i][v] + wsum[1][i][v] + wsum[2][i][v] + wsum[3][i][v];
+    }
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ psi, const double2* __restrict__ tlo,
@@ -830,12 +921,23 @@ __global__ __launch_bounds__(256) void k_overlap(const typename CT<TA>::c* __res
     }
 }
 
-__global__ void k_finalize(const double* __restrict__ partials, int nblocks, int nvals, double* __restrict__ out) {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nvals) return;
+// One workgroup per output value: thread t sums partial rows t, t + 256, ...
+// in order, then a fixed LDS tree adds the 256 thread sums, so the result
+// does not depend on timing.
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials, int nblocks, int nvals,
+                                                  double* __restrict__ out) {
+    __shared__ double red[256];
+    const int v = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * nvals + v];
-    out[v] = s;
+    for (int b = threadIdx.x; b < nblocks; b += 256) s += partials[(size_t)b * nvals + v];
+    red[threadIdx.x] = s;
+    __syncthreads();
+#pragma unroll
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1283,8 +1385,15 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
     return hipGetLastError();
 }
 
+hipError_t launch_rdm_win(const fl_geom& g, const void* psi, const fl_win& pw, double* partials, int grid, int nslot,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(k_rdm_win<FL_KMAX_RDM - FL_LOWBITS>, dim3(grid), dim3(256), 0, s, (const float2*)psi,
+                       ntiles_of(g), pw, partials, nslot);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* partials, int nblocks, int nvals, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize, dim3((nvals + 255) / 256), dim3(256), 0, s, partials, nblocks, nvals, out);
+    hipLaunchKernelGGL(k_finalize, dim3(nvals), dim3(256), 0, s, partials, nblocks, nvals, out);
     return hipGetLastError();
 }
 

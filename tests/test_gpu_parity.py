@@ -122,7 +122,7 @@ def test_small_chains_element_by_element(dtype, L):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("L", [2, 6, 13, 16])
+@pytest.mark.parametrize("L", [2, 6, 13, 16, 21])
 def test_rdm_energy_and_spread_match_oracle(dtype, L):
     say(f"case: rdm L={L} {dtype}")
     w, hs = _model(L, seed=7)
