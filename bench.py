@@ -34,18 +34,30 @@ PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 # HBM bytes per sweep launch from two rocprofv3 --pmc runs (FETCH_SIZE, then
 # WRITE_SIZE) of "bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-adjoint
-# --calibrate-copy", each scaled by what the counter reads for the plain 8 GiB
-# device copy in the same run (FETCH_SIZE read 4.0 GiB -> x2; WRITE_SIZE read
-# 8.0 GiB -> x1).  Valid only for the kernel source it was taken on.
-TRAFFIC = {"kernels_sha256_16": "5c4356ae130362fe", "fetch_gib_raw": 4.0, "fetch_scale": 2.0,
+# --no-l34 --calibrate-copy", each scaled by what the counter reads for the
+# plain 8 GiB device copy in the same run (FETCH_SIZE read 4.0 GiB -> x2;
+# WRITE_SIZE read 8.0 GiB -> x1).  Valid only for the kernel code it was taken
+# on: the key is a hash of kernels.hip and fl_common.h with comments and
+# whitespace removed.
+TRAFFIC = {"kernel_code_sha256_16": "dbceea998503c92b", "fetch_gib_raw": 4.0002, "fetch_scale": 2.0,
            "write_gib_raw": 8.0, "write_scale": 1.0}
 
 
-def measured_traffic():
+def kernel_code_hash():
     import hashlib
-    with open(os.path.join(ROOT, "paper_2111_08044_amd", "csrc", "kernels.hip"), "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()[:16]
-    if sha != TRAFFIC["kernels_sha256_16"]:
+    import re
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "fl_common.h"):
+        with open(os.path.join(ROOT, "paper_2111_08044_amd", "csrc", name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    if kernel_code_hash() != TRAFFIC["kernel_code_sha256_16"]:
         return None
     gib = TRAFFIC["fetch_gib_raw"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_gib_raw"] * TRAFFIC["write_scale"]
     return gib * 2**30

@@ -9,7 +9,7 @@
 // (b, b+1) and therefore the two bits p = L-2-b and p+1; the 4x4 gate acts on
 // the local index 2*bit(p+1) + bit(p).
 //
-// A "pass" streams the whole state through LDS once.  The amplitudes are
+// A "pass" streams the whole state through the chip once.  The amplitudes are
 // split into tiles of 2^K that share every bit outside a tile bit set
 // S = [0, C) u [h, h+W) (K = C + W); the C low bits keep every tile made of
 // 2^W contiguous runs of 2^C amplitudes, so loads and stores coalesce.  Inside

@@ -1,16 +1,24 @@
 // HIP kernels of the Floquet brickwork engine (gfx950, wave64).
 //
-//  k_sweep    fused gate sweep: one HBM read + write of the state applies
+//  k_sweep_tiles / k_sweep
+//             fused gate sweep: one HBM read + write of the state applies
 //             every gate of a pass (Sec. II Eq. (2), fused as in Sec. II).
-//  k_rdm      two-site reduced density matrices of every bond in a pass plus
-//             the norm, FP64 accumulation (Sec. II Eq. (1); Sec. IV Eq. (10)).
+//  k_rdm_tiles / k_rdm_win / k_rdm
+//             two-site reduced density matrices of the bonds of a pass (plus
+//             the norm), FP64 accumulation (Sec. II Eq. (1); Sec. IV Eq. (10)).
+//  k_apply_h  lambda = H0 psi, out of place (Sec. IV Eq. (11), Sec. V).
+//  k_adjoint  reverse replay with G^dagger and the overlap terms of the
+//             gradient of <H0>.
+//  k_dense6   pre-multiplied 6-qubit windows on the matrix cores (FP32 or
+//             split BF16x3, Sec. II on half-precision matrix units).
 //  k_init     product initial state (Sec. IV Eq. (9) form; product of spinors).
 //  k_overlap  <phi|psi> and both norms across precisions (Sec. V echo measure).
 //  k_finalize deterministic sum of per-workgroup partials.
 //
-// Tile kernels stage a tile of 2^K amplitudes in LDS (see fl_common.h for
-// the geometry), then each thread loads 2^R amplitudes of one register group
-// into VGPRs, applies the group's 4x4 gates there and writes them back.
+// Tile kernels hold a tile of 2^K amplitudes (see fl_common.h for the
+// geometry); each thread keeps 2^R amplitudes of one register group in VGPRs,
+// applies the group's 4x4 gates there, and the tile changes register layout
+// between groups through LDS.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
