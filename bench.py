@@ -74,10 +74,14 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
-                         "variants against an FP64 GPU run (precision), or the echo overlap error (echo)")
+                         "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
+                         "or heating of the paper's GUE circuit versus drive frequency (gue)")
     ap.add_argument("--max-periods", type=int, default=10000)
+    ap.add_argument("--omegas", type=str, default="5,5.5,6,6.5,7,7.5,8",
+                    help="drive frequencies of --study gue")
+    ap.add_argument("--tmax", type=float, default=2e5, help="longest time (units of 1/J) of --study gue")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the state once (a plain device copy of known size, the reference "
                          "for scaling hardware byte counters)")
@@ -238,6 +242,66 @@ def echo_study(fl, torch, L, nmax):
     return {"study": "echo", "L": L, "rows": rows}
 
 
+def gue_study(fl, torch, L, omegas, tmax, nrec=240):
+    """The paper's own model (Sec. III A, IV): GUE bond terms H_k (one seeded
+    sample), gates exp(-i H_k T) with T = 2 pi / omega, the ground state of H_o
+    as the initial state; E(t) and sigma_E(t) of H-bar = sum_k H_k on
+    log-spaced periods, and the heating rate Gamma = 1/(t2 - t1) with
+    E(t_k) = E(0) exp(-k).  complex64 plain sweep.  A run stops once E/E(0)
+    falls below exp(-2.5) or t reaches tmax."""
+    import numpy as np
+
+    import floquet_inputs as fin
+    Hk = fin.gue_bond_sample(L)
+    eng = fl.FloquetEngine(L, "c64")
+    psi, ws = eng.new_state(), eng.new_state()
+    out = []
+    for om in omegas:
+        T = 2.0 * np.pi / om
+        eng.set_paper_model(Hk, om)
+        eng.init_ground_pairs(psi)
+        nmax = int(np.ceil(tmax / T))
+        recs = np.unique(np.round(np.logspace(0, np.log10(nmax), nrec)).astype(np.int64))
+        t_s, E_s, S_s = [], [], []
+
+        def record(n):
+            sig, e, _ = eng.energy_spread(psi, ws)   # of H0 = 2 H-bar
+            t_s.append(n * T)
+            E_s.append(0.5 * e)
+            S_s.append(0.5 * sig)
+
+        record(0)
+        n, t0 = 0, time.perf_counter()
+        for r in recs:
+            eng.step(psi, int(r - n))
+            n = int(r)
+            record(n)
+            if E_s[-1] / E_s[0] < np.exp(-2.5):
+                break
+        torch.cuda.synchronize()
+        G, t1, t2 = fl.thermalization_rate(t_s, E_s)
+        row = {"omega": om, "T": T, "periods": n, "t_end": n * T, "seconds": round(time.perf_counter() - t0, 2),
+               "E0": E_s[0], "sigma0": S_s[0], "E_end": E_s[-1], "sigma_end": S_s[-1],
+               "gamma": G, "t1": t1, "t2": t2,
+               "series": {"t": [round(x, 4) for x in t_s], "E_over_E0": [round(x / E_s[0], 6) for x in E_s],
+                          "sigma": [round(x, 6) for x in S_s]}}
+        print(json.dumps({k: v for k, v in row.items() if k != "series"}), file=sys.stderr, flush=True)
+        out.append(row)
+    fit_rows = [r for r in out if r["gamma"] is not None]
+    fit = None
+    if len(fit_rows) >= 2:
+        a, b = fl.fit_exponential_rate([r["omega"] for r in fit_rows], [r["gamma"] for r in fit_rows])
+        fit = {"a": a, "b": b, "omegas": [r["omega"] for r in fit_rows]}
+    # infinite-temperature spread: tr(H-bar^2) / 2^L = sum_k |H_k|_F^2 / 4
+    # + 2 sum_k tr(R_k L_{k+1}) / 8 (R_k, L_k: H_k traced over its left / right
+    # site; terms further apart vanish because every H_k is traceless)
+    R4 = [np.einsum("aiaj->ij", H.reshape(2, 2, 2, 2)) for H in Hk]
+    L4 = [np.einsum("iaja->ij", H.reshape(2, 2, 2, 2)) for H in Hk]
+    var = np.sum(np.abs(Hk) ** 2) / 4.0 + 2.0 * sum(np.trace(R4[k] @ L4[k + 1]).real for k in range(L - 2)) / 8.0
+    return {"study": "gue", "L": L, "seed": fin.DEFAULT_SEED, "tmax": tmax,
+            "sigma_inf": float(np.sqrt(var)), "fit": fit, "rows": out}
+
+
 def l34_leg(fl, torch, periods=16):
     """L = 34 complex64 (128 GiB) in place: periods/s of the plain sweep and
     the energy density after the run."""
@@ -289,6 +353,10 @@ def main():
         return
     if args.study == "echo":
         print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
+        return
+    if args.study == "gue":
+        omegas = [float(x) for x in args.omegas.split(",")]
+        print(json.dumps(gue_study(fl, torch, L, omegas, args.tmax)), flush=True)
         return
     w = fin.xyz_workload(L)
     eng = fl.FloquetEngine(L, "c64")

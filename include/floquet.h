@@ -98,6 +98,17 @@ int fl_set_gates(fl_ctx *ctx, const double *G, const double *h, double T);
  * [L][2] complex (double re, im), site-major.  Asynchronous. */
 int fl_init_state(fl_ctx *ctx, void *psi, const double *spinors);
 
+/* Write the pair-product state of Sec. IV, Eq. (9): the sites (2m, 2m+1)
+ * carry the two-site state pairs[m], so that
+ *   psi[x] = prod_m pairs[m][2 bit(site 2m) + bit(site 2m+1)]
+ * (the paper's initial state is the ground state of every odd-k term, i.e.
+ * pairs[m] = ground state of h_{2m}; see fl_host_ground_states).  For odd L
+ * the last site is unpaired and carries the spinor tail.  FP64, rounded.
+ * psi: device, 2^L amplitudes of the context dtype.  pairs: host [L/2][4]
+ * complex; tail: host [2] complex, required for odd L, ignored for even L.
+ * Errors: FL_EINVAL (NULL, non-finite), FL_EHIP.  Asynchronous. */
+int fl_init_pairs(fl_ctx *ctx, void *psi, const double *pairs, const double *tail);
+
 /* psi <- U_F^n psi (dagger = 0) or psi <- (U_F^dagger)^n psi (dagger = 1),
  * in place (Sec. III A, Eq. (3)-(4); the time-reversed evolution of the echo
  * of Sec. V).  n_periods >= 0.  Asynchronous. */
@@ -155,6 +166,12 @@ int fl_xyz_bonds(int L, const double *J, const double *fields, double *h_out);
 
 /* The FP64 gates the library builds: G_out[b] = exp(-i (T/2) h[b]), [n][4][4] complex. */
 int fl_host_gates(int nbonds, const double *h, double T, double *G_out);
+
+/* Ground states of n two-site Hamiltonians h [n][4][4] (complex, Hermitian):
+ * g_out[k] = the eigenvector of the lowest eigenvalue of h[k] ([n][4]
+ * complex, unit norm, largest component real and positive), e_out[k] (may
+ * be NULL) = that eigenvalue.  FP64 Jacobi; errors: FL_EINVAL. */
+int fl_host_ground_states(int n, const double *h, double *g_out, double *e_out);
 
 /* d/dtheta exp(-i (T/2) h(theta)) in direction gen (4x4 complex each). */
 int fl_host_gate_derivative(const double *h, const double *gen, double T, double *dG_out);

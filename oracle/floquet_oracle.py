@@ -89,6 +89,35 @@ def product_state(spinors):
     return psi
 
 
+def ground_state(h):
+    """Lowest eigenvector of a Hermitian two-site term (and its eigenvalue),
+    unit norm, with its largest component made real and positive."""
+    lam, V = np.linalg.eigh(np.asarray(h, dtype=np.complex128))
+    g = V[:, 0]
+    k = int(np.argmax(np.abs(g)))
+    g = g * (np.conj(g[k]) / abs(g[k]))
+    return g / np.linalg.norm(g), lam[0]
+
+
+def pair_product_state(pairs, tail=None):
+    """|psi(0)> = (x)_m |d_m> with |d_m> on sites (2m, 2m+1) (Sec. IV, Eq. (9):
+    the ground state of the odd-k terms is such a product of two-site ground
+    states); for odd L the last site carries the spinor `tail`."""
+    psi = np.array([1.0 + 0j])
+    for d in pairs:
+        psi = np.kron(psi, np.asarray(d, dtype=np.complex128))
+    if tail is not None:
+        psi = np.kron(psi, np.asarray(tail, dtype=np.complex128))
+    return psi
+
+
+def paper_model(Hk, omega):
+    """The paper's circuit (Sec. III A) in this module's conventions: the gate
+    exp(-i H_k T) of Eq. (5) is exp(-i (T/2) h_b) with h_b = 2 H_k, and T = 2 pi / omega.
+    Returns (h_b list, T).  Its time-averaged Hamiltonian is sum_k H_k = H0 / 2."""
+    return [2.0 * np.asarray(H, dtype=np.complex128) for H in Hk], 2.0 * np.pi / omega
+
+
 def layer_bonds(L, dagger=False):
     """The two layers of one period in application order.
 

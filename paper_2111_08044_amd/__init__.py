@@ -23,10 +23,12 @@ from ._native import (FL_C64, FL_C128, FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X
                       FloquetError, check, lib)
 
 __all__ = [
-    "fl_create", "fl_destroy", "fl_set_bonds", "fl_set_gates", "fl_init_state", "fl_apply_period",
+    "fl_create", "fl_destroy", "fl_set_bonds", "fl_set_gates", "fl_init_state", "fl_init_pairs", "fl_apply_period",
     "fl_expect_energy", "fl_energy_spread", "fl_overlap", "fl_grad_workspace_bytes", "fl_grad",
     "fl_last_error", "fl_xyz_bonds", "fl_xyz_generators", "fl_host_gates", "fl_host_gate_derivative",
+    "fl_host_ground_states",
     "fl_plan_query", "fl_tile_map", "fl_host_window_matrix", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
+    "thermalization_rate", "fit_exponential_rate",
 ]
 
 _DTYPES = {"c64": FL_C64, "c128": FL_C128}
@@ -128,6 +130,14 @@ def fl_init_state(ctx: Context, psi, spinors):
     check(lib().fl_init_state(ctx.handle, _state_ptr(ctx, psi), _dp(s)))
 
 
+def fl_init_pairs(ctx: Context, psi, pairs, tail=None):
+    """psi <- prod_m pairs[m] on sites (2m, 2m+1) (and tail on the last site for odd L)."""
+    p = _c16(pairs, (ctx.L // 2, 4))
+    t = _c16(tail, (2,)) if tail is not None else None
+    _stream(ctx)
+    check(lib().fl_init_pairs(ctx.handle, _state_ptr(ctx, psi), _dp(p), _dp(t) if t is not None else None))
+
+
 def fl_apply_period(ctx: Context, psi, n: int, dagger: bool = False):
     _stream(ctx)
     check(lib().fl_apply_period(ctx.handle, _state_ptr(ctx, psi), int(n), 1 if dagger else 0))
@@ -221,6 +231,17 @@ def fl_host_gate_derivative(h, gen, T: float) -> np.ndarray:
     return out
 
 
+def fl_host_ground_states(h):
+    """(g, e0): lowest eigenvectors (n, 4) and eigenvalues (n,) of n 4x4 Hermitian matrices."""
+    h = np.asarray(h, dtype=np.complex128)
+    n = h.reshape(-1, 4, 4).shape[0]
+    hb = _c16(h, (n, 4, 4))
+    g = np.zeros((n, 4), dtype=np.complex128)
+    e = np.zeros(n)
+    check(lib().fl_host_ground_states(n, _dp(hb), _dp(g.view(np.float64)), _dp(e)))
+    return g, e
+
+
 def fl_host_window_matrix(G, pos, mode=None):
     """(U, fragments) of a dense window: U = E(op_n-1)...E(op_0) (64x64) and, for
     mode 0/1, the 64 KiB of MFMA fragments as raw bytes."""
@@ -253,4 +274,4 @@ def fl_tile_map(L: int, dtype="c64", h: int = 0) -> np.ndarray:
     return out
 
 
-from .engine import FloquetEngine, FloquetEnergy  # noqa: E402
+from .engine import FloquetEngine, FloquetEnergy, fit_exponential_rate, thermalization_rate  # noqa: E402

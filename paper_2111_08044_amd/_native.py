@@ -30,6 +30,7 @@ SIGNATURES = {
     "fl_set_bonds": (C.c_int, [vp, dp, C.c_double]),
     "fl_set_gates": (C.c_int, [vp, dp, dp, C.c_double]),
     "fl_init_state": (C.c_int, [vp, vp, dp]),
+    "fl_init_pairs": (C.c_int, [vp, vp, dp, dp]),
     "fl_apply_period": (C.c_int, [vp, vp, i64, C.c_int]),
     "fl_expect_energy": (C.c_int, [vp, vp, dp, dp]),
     "fl_energy_spread": (C.c_int, [vp, vp, vp, dp]),
@@ -40,6 +41,7 @@ SIGNATURES = {
     "fl_xyz_bonds": (C.c_int, [C.c_int, dp, dp, dp]),
     "fl_host_gates": (C.c_int, [C.c_int, dp, C.c_double, dp]),
     "fl_host_gate_derivative": (C.c_int, [dp, dp, C.c_double, dp]),
+    "fl_host_ground_states": (C.c_int, [C.c_int, dp, dp, dp]),
     "fl_xyz_generators": (C.c_int, [C.c_int, dp]),
     "fl_tile_map": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_uint64)]),
     "fl_host_window_matrix": (C.c_int, [dp, C.POINTER(C.c_int), C.c_int, C.c_int, dp, vp]),

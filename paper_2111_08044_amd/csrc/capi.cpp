@@ -492,6 +492,41 @@ int fl_init_state(fl_ctx* c, void* psi, const double* spinors) {
     return FL_OK;
 }
 
+int fl_init_pairs(fl_ctx* c, void* psi, const double* pairs, const double* tail) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (!pairs) return fail(FL_EINVAL, "pairs is NULL");
+    const int L = c->L, np = L / 2;
+    if ((L & 1) && !tail) return fail(FL_EINVAL, "odd L needs the spinor of the last site (tail)");
+    if (!finite_all(pairs, (size_t)np * 8) || ((L & 1) && !finite_all(tail, 4)))
+        return fail(FL_EINVAL, "pairs/tail have non-finite entries");
+    std::vector<cd> pv((size_t)4 * np), tv(2, cd(1.0));
+    for (int i = 0; i < 4 * np; ++i) pv[i] = cd(pairs[2 * i], pairs[2 * i + 1]);
+    if (L & 1)
+        for (int i = 0; i < 2; ++i) tv[i] = cd(tail[2 * i], tail[2 * i + 1]);
+    // table boundaries on pair boundaries: even for even L, odd for odd L
+    int a = std::min(L, 12), b = std::min(L - a, 12);
+    if (L & 1) {
+        a = std::min(L, 11);
+        b = std::min(L - a, 12);
+    }
+    std::vector<cd> tlo, tmid, thi;
+    if (!fl::pair_tables(L, pv.data(), tv.data(), a, b, tlo, tmid, thi))
+        return fail(FL_EINVAL, "internal: pair table boundary");
+    std::vector<double> buf;
+    for (auto* t : {&tlo, &tmid, &thi})
+        for (const cd& z : *t) {
+            buf.push_back(z.real());
+            buf.push_back(z.imag());
+        }
+    FL_HIP(hipMemcpyAsync(c->d_tabs, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipError_t e = fl::launch_init(c->dtype, psi, L, c->d_tabs, a, b, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_init launch");
+    FL_HIP(hipStreamSynchronize(c->stream));
+    return FL_OK;
+}
+
 int fl_apply_period(fl_ctx* c, void* psi, int64_t n, int dagger) {
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
     int rc = check_state(c, psi, "psi");
@@ -699,6 +734,23 @@ int fl_host_gates(int nb, const double* h, double T, double* G_out) {
             G_out[(size_t)b * 32 + 2 * k] = G[k].real();
             G_out[(size_t)b * 32 + 2 * k + 1] = G[k].imag();
         }
+    }
+    return FL_OK;
+}
+
+int fl_host_ground_states(int n, const double* h, double* g_out, double* e_out) {
+    if (n < 1 || !h || !g_out) return fail(FL_EINVAL, "bad argument");
+    if (!finite_all(h, (size_t)n * 32)) return fail(FL_EINVAL, "h has non-finite entries");
+    for (int k = 0; k < n; ++k) {
+        cd hm[16], g[4];
+        double e0 = 0.0;
+        read_c16(h + (size_t)k * 32, hm);
+        fl::ground_state4(hm, g, &e0);
+        for (int i = 0; i < 4; ++i) {
+            g_out[(size_t)k * 8 + 2 * i] = g[i].real();
+            g_out[(size_t)k * 8 + 2 * i + 1] = g[i].imag();
+        }
+        if (e_out) e_out[k] = e0;
     }
     return FL_OK;
 }

@@ -260,4 +260,46 @@ void product_tables(int L, const cd* spinors, int a, int b, std::vector<cd>& tlo
     build(a + b, L - a - b, thi);
 }
 
+void ground_state4(const cd* h, cd* g, double* e0) {
+    double lam[4];
+    cd V[16];
+    herm_eig4(h, lam, V);
+    int j = 0;
+    for (int k = 1; k < 4; ++k)
+        if (lam[k] < lam[j]) j = k;
+    int big = 0;
+    for (int i = 1; i < 4; ++i)
+        if (std::abs(V[4 * i + j]) > std::abs(V[4 * big + j])) big = i;
+    const cd ph = std::conj(V[4 * big + j]) / std::abs(V[4 * big + j]);
+    double nrm = 0.0;
+    for (int i = 0; i < 4; ++i) nrm += std::norm(V[4 * i + j]);
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < 4; ++i) g[i] = V[4 * i + j] * ph / nrm;
+    if (e0) *e0 = lam[j];
+}
+
+bool pair_tables(int L, const cd* pairs, const cd* tail, int a, int b, std::vector<cd>& tlo,
+                 std::vector<cd>& tmid, std::vector<cd>& thi) {
+    // bit q of x belongs to site L-1-q; pair m holds sites (2m, 2m+1), i.e.
+    // bits qa = L-1-2m (the high bit of its local index) and qb = qa-1
+    const int npairs = L / 2;
+    auto build = [&](int q0, int n, std::vector<cd>& t) -> bool {
+        t.assign((size_t)1 << n, cd(1.0));
+        for (int m = 0; m < npairs; ++m) {
+            const int qa = L - 1 - 2 * m, qb = qa - 1;
+            const bool ia = qa >= q0 && qa < q0 + n, ib = qb >= q0 && qb < q0 + n;
+            if (ia != ib) return false;   // a boundary would split the pair
+            if (!ia) continue;
+            for (int v = 0; v < (1 << n); ++v) {
+                const int loc = 2 * ((v >> (qa - q0)) & 1) + ((v >> (qb - q0)) & 1);
+                t[v] *= pairs[4 * m + loc];
+            }
+        }
+        if ((L & 1) && q0 == 0 && n > 0)   // the unpaired last site is bit 0
+            for (int v = 0; v < (1 << n); ++v) t[v] *= tail[v & 1];
+        return true;
+    };
+    return build(0, a, tlo) && build(a, b, tmid) && build(a + b, L - a - b, thi);
+}
+
 }  // namespace fl

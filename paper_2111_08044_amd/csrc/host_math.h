@@ -44,4 +44,15 @@ void product_tables(int L, const std::complex<double>* spinors, int a, int b,
                     std::vector<std::complex<double>>& tlo, std::vector<std::complex<double>>& tmid,
                     std::vector<std::complex<double>>& thi);
 
+// Lowest eigenvector of a 4x4 Hermitian h (unit norm, largest component real
+// and positive); *e0 (if not NULL) receives its eigenvalue.
+void ground_state4(const std::complex<double>* h, std::complex<double>* g, double* e0);
+
+// Factor tables (as product_tables) of the pair-product state
+// psi[x] = prod_m pairs[m][2 bit(site 2m) + bit(site 2m+1)] (* tail[bit(site L-1)]
+// for odd L).  false if a table boundary (a or a+b) would split a pair.
+bool pair_tables(int L, const std::complex<double>* pairs, const std::complex<double>* tail, int a, int b,
+                 std::vector<std::complex<double>>& tlo, std::vector<std::complex<double>>& tmid,
+                 std::vector<std::complex<double>>& thi);
+
 }  // namespace fl

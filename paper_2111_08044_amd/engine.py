@@ -4,8 +4,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import (fl_apply_period, fl_create, fl_energy_spread, fl_expect_energy, fl_grad, fl_init_state,
-               fl_overlap, fl_set_bonds, fl_xyz_bonds, fl_xyz_generators, new_state)
+from . import (fl_apply_period, fl_create, fl_energy_spread, fl_expect_energy, fl_grad, fl_host_ground_states,
+               fl_init_pairs, fl_init_state, fl_overlap, fl_set_bonds, fl_xyz_bonds, fl_xyz_generators, new_state)
 
 
 class FloquetEngine:
@@ -16,7 +16,14 @@ class FloquetEngine:
         self.ctx = fl_create(L, dtype, variant)
 
     def set_bonds(self, h, T: float):
-        fl_set_bonds(self.ctx, h, T)
+        self.h = np.asarray(h, dtype=np.complex128).reshape(self.L - 1, 4, 4).copy()
+        fl_set_bonds(self.ctx, self.h, T)
+
+    def set_paper_model(self, Hk, omega: float):
+        """The paper's circuit (Sec. III A): gates exp(-i H_k T), T = 2 pi / omega,
+        i.e. bond Hamiltonians h_b = 2 H_k for the half-period gate exp(-i (T/2) h_b).
+        The energy observable is then H0 = 2 H-bar (H-bar = sum_k H_k)."""
+        self.set_bonds(2.0 * np.asarray(Hk, dtype=np.complex128), 2.0 * np.pi / omega)
 
     def set_xyz(self, J, fields, T: float):
         self.set_bonds(fl_xyz_bonds(self.L, J, fields), T)
@@ -26,6 +33,16 @@ class FloquetEngine:
 
     def init(self, psi, spinors):
         fl_init_state(self.ctx, psi, spinors)
+
+    def init_pairs(self, psi, pairs, tail=None):
+        fl_init_pairs(self.ctx, psi, pairs, tail)
+
+    def init_ground_pairs(self, psi, tail=None):
+        """The paper's initial state (Sec. IV, Eq. (9)): the ground state of
+        every odd-k term (0-indexed even bond b) on its two sites; for odd L
+        the last site carries `tail`."""
+        g, _ = fl_host_ground_states(self.h[0::2][: self.L // 2])
+        fl_init_pairs(self.ctx, psi, g, tail)
 
     def step(self, psi, n: int = 1, dagger: bool = False):
         fl_apply_period(self.ctx, psi, n, dagger)
@@ -59,6 +76,35 @@ class FloquetEngine:
             E, N = self.energy(psi)
             rows.append((t, E / (self.L * N), E / self.L, N))
         return rows
+
+
+def thermalization_rate(t, E, k1: int = 1, k2: int = 2):
+    """Heating rate of Sec. IV: Gamma = 1 / (t_k2 - t_k1), where t_k is the
+    first time at which E(t) = E(0) exp(-k), E measured from the
+    infinite-temperature value 0 (traceless bond terms).  Crossings are
+    interpolated linearly between samples.  Returns (Gamma, t_k1, t_k2), with
+    None entries when E(t) does not get that far."""
+    t = np.asarray(t, dtype=float)
+    r = np.asarray(E, dtype=float) / float(E[0])
+
+    def crossing(k):
+        lvl = np.exp(-k)
+        below = np.nonzero(r <= lvl)[0]
+        if below.size == 0 or below[0] == 0:
+            return None
+        i = below[0]
+        return t[i - 1] + (r[i - 1] - lvl) / (r[i - 1] - r[i]) * (t[i] - t[i - 1])
+
+    t1, t2 = crossing(k1), crossing(k2)
+    if t1 is None or t2 is None or t2 <= t1:
+        return None, t1, t2
+    return 1.0 / (t2 - t1), t1, t2
+
+
+def fit_exponential_rate(omegas, gammas):
+    """(a, b) of the least-squares fit log Gamma = a omega + b (Sec. IV)."""
+    a, b = np.polyfit(np.asarray(omegas, dtype=float), np.log(np.asarray(gammas, dtype=float)), 1)
+    return float(a), float(b)
 
 
 def _torch():

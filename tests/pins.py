@@ -251,3 +251,39 @@ def ising_gradient_error(O, L, n, seed=29):
     for b in range(L - 1):
         err += abs(grad[b * 3 + 2] - r[b][2] * r[b + 1][2])
     return err
+
+
+def paper_model_error(O, L, omega, seed=31):
+    """Largest error of the paper's model in the oracle (Sec. III A-B, IV):
+    - U_F^3 v against exp(-i H_o T) exp(-i H_e T) built densely from the GUE
+      terms H_k (odd k = even b first in H_o);
+    - E(0) of the pair-product ground state of H_o against the closed form
+      sum_{odd k} E_gs(H_k) + sum_{even k} tr(h_b (rho_right(m) (x) rho_left(m+1)));
+    - the odd-k bond density matrices against the pure pair states."""
+    import scipy.linalg as sla
+    Hk = np.asarray(fin.gue_bond_sample(L, seed))
+    hs, T = O.paper_model(Hk, omega)
+    Ho = sum(O.embed_bond(L, b, Hk[b]) for b in range(0, L - 1, 2))
+    He = sum(O.embed_bond(L, b, Hk[b]) for b in range(1, L - 1, 2))
+    UF = sla.expm(-1j * Ho * T) @ sla.expm(-1j * He * T)
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(1 << L) + 1j * rng.standard_normal(1 << L)
+    err = np.max(np.abs(O.evolve(v, L, O.floquet_gates(hs, T), 3) - np.linalg.matrix_power(UF, 3) @ v))
+    gs = [O.ground_state(hs[b]) for b in range(0, L - 1, 2)]
+    tail = np.array([0.6, 0.8j]) if L % 2 else None
+    psi0 = O.pair_product_state([g for g, _ in gs], tail)
+    E, N = O.energy(psi0, L, hs)
+    rho = [np.outer(g, g.conj()).reshape(2, 2, 2, 2) for g, _ in gs]
+    left = [np.einsum("iaja->ij", r) for r in rho]
+    right = [np.einsum("aiaj->ij", r) for r in rho]
+    if tail is not None:
+        left.append(np.outer(tail, tail.conj()))
+    Eref = sum(e for _, e in gs)
+    for b in range(1, L - 1, 2):
+        m = b // 2
+        Eref += np.trace(hs[b] @ np.kron(right[m], left[m + 1])).real
+    err = max(err, abs(N - 1.0), abs(E - Eref))
+    for b in range(0, L - 1, 2):
+        g = gs[b // 2][0]
+        err = max(err, np.max(np.abs(O.bond_rdm(psi0, L, b) - np.outer(g, g.conj()))))
+    return err

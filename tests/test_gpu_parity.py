@@ -151,6 +151,50 @@ def test_rdm_energy_and_spread_match_oracle(dtype, L):
         assert np.max(np.abs(ws.cpu().numpy() - hv)) < 1e-12 * np.max(np.abs(hv))
 
 
+# ------------------------------------------- the paper's own model (Sec. III A, IV)
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("L", [12, 13])
+def test_pair_init_matches_oracle(dtype, L):
+    say(f"case: pair init L={L} {dtype}")
+    hs = O.paper_model(fin.gue_bond_sample(L), 6.0)[0]
+    pairs = [O.ground_state(hs[b])[0] for b in range(0, L - 1, 2)]
+    tail = np.array([0.6, 0.8j]) if L % 2 else None
+    ctx = fl.fl_create(L, dtype)
+    psi = _gpu_state(ctx)
+    fl.fl_init_pairs(ctx, psi, np.array(pairs), tail)
+    ref = O.pair_product_state(pairs, tail)
+    tol = 1e-15 if dtype == "c128" else 1e-7
+    assert np.max(np.abs(psi.cpu().numpy() - ref)) < tol
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 40), ("c64", 300)])
+def test_paper_model_circuit_matches_oracle(dtype, n):
+    """The paper's GUE circuit at omega = 6 from the ground state of H_o:
+    state, E and sigma_E against the oracle (FP64: state L2 1e-12; FP32:
+    energy density 1e-5)."""
+    L, omega = 12, 6.0
+    say(f"case: paper model L={L} {dtype} n={n}")
+    Hk = fin.gue_bond_sample(L)
+    hs, T = O.paper_model(Hk, omega)
+    eng = fl.FloquetEngine(L, dtype)
+    eng.set_paper_model(Hk, omega)
+    psi = eng.new_state()
+    eng.init_ground_pairs(psi)
+    ref = O.pair_product_state([O.ground_state(hs[b])[0] for b in range(0, L - 1, 2)])
+    ref = O.evolve(ref, L, O.floquet_gates(hs, T), n)
+    eng.step(psi, n)
+    got = psi.cpu().numpy().astype(np.complex128)
+    if dtype == "c128":
+        assert np.linalg.norm(got - ref) < 1e-12
+    e_ref = O.energy_density(ref, L, hs)
+    assert abs(eng.energy_density(psi) - e_ref) < (1e-12 if dtype == "c128" else 1e-5)
+    ws = eng.new_state()
+    sig, e1, e2 = eng.energy_spread(psi, ws)
+    sig_ref = O.energy_spread(ref, L, hs)[0]
+    assert abs(sig - sig_ref) < (1e-10 if dtype == "c128" else 1e-4) * max(1.0, sig_ref)
+
+
 def test_overlap_mixed_precision():
     L = 15
     rng = np.random.default_rng(3)

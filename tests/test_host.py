@@ -81,6 +81,35 @@ def test_host_gates_degenerate_and_gue_spectra():
         assert np.max(np.abs(G - sla.expm(-0.125j * h))) < 1e-13
 
 
+def test_host_ground_states_match_oracle():
+    """Lowest eigenvectors of the paper's GUE terms and of the Heisenberg
+    bond (singlet at -3), with the same phase convention as the oracle."""
+    P = O.PAULIS
+    hs = np.array([sum(np.kron(p, p) for p in P)] + list(2.0 * fin.gue_bond_sample(12)))
+    g, e = fl.fl_host_ground_states(hs)
+    assert abs(e[0] + 3.0) < 1e-13
+    for k in range(len(hs)):
+        go, eo = O.ground_state(hs[k])
+        assert abs(e[k] - eo) < 1e-13
+        assert np.max(np.abs(g[k] - go)) < 1e-12
+        assert np.max(np.abs(hs[k] @ g[k] - e[k] * g[k])) < 1e-13
+
+
+def test_thermalization_rate_closed_form():
+    """E(t) = E0 on a plateau up to t0, then E0 exp(-Gamma (t - t0)): the
+    crossings of E0/e and E0/e^2 are 1/Gamma apart (Sec. IV)."""
+    for gamma, t0 in ((0.3, 5.0), (1.3e-4, 200.0)):
+        t = np.linspace(0.0, t0 + 4.0 / gamma, 200001)
+        E = -2.0 * np.exp(-gamma * np.clip(t - t0, 0.0, None))
+        G, t1, t2 = fl.thermalization_rate(t, E)
+        assert abs(G / gamma - 1.0) < 1e-6
+        assert abs(t1 - (t0 + 1.0 / gamma)) < 1e-4 / gamma
+    G, t1, t2 = fl.thermalization_rate([0, 1, 2], [-1.0, -0.5, -0.3])
+    assert G is None and t1 is not None and t2 is None
+    a, b = fl.fit_exponential_rate([5, 6, 7, 8], np.exp(-2.48 * np.array([5, 6, 7, 8]) + 10.9))
+    assert abs(a + 2.48) < 1e-12 and abs(b - 10.9) < 1e-10
+
+
 def test_host_gate_derivative_matches_expm_frechet():
     L = 6
     w = fin.xyz_workload(L)

@@ -10,6 +10,7 @@ import types
 
 import numpy as np
 import pytest
+import scipy.linalg as sla
 
 import floquet_inputs as fin
 import oracle as O
@@ -135,6 +136,37 @@ def test_gue_sample_is_traceless_with_frobenius_norm_sqrt2():
         assert abs(np.linalg.norm(h) - np.sqrt(2.0)) < 1e-14
     # "first L-1 entries of one long list" (Sec. III A)
     assert np.array_equal(fin.gue_bond_sample(5), H[:4])
+
+
+# ------------------------------------------- the paper's own model (Sec. III A, IV)
+
+def test_ground_state_special_cases():
+    # Heisenberg XX + YY + ZZ = 2 SWAP - 1: the singlet (|01> - |10>)/sqrt2 at -3
+    P = O.PAULIS
+    h = sum(np.kron(p, p) for p in P)
+    g, e0 = O.ground_state(h)
+    assert abs(e0 + 3.0) < 1e-13
+    assert abs(abs(np.vdot(g, np.array([0, 1, -1, 0]) / np.sqrt(2))) - 1.0) < 1e-13
+    # a diagonal term: the basis vector of the smallest diagonal entry
+    g, e0 = O.ground_state(np.diag([3.0, 1.0, -2.0, 5.0]).astype(complex))
+    assert e0 == -2.0 and abs(abs(g[2]) - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("L", [6, 7])
+def test_pair_product_state_reduces_to_product_state(L):
+    s = fin.xyz_workload(L)["spinors"]
+    pairs = [np.kron(s[2 * m], s[2 * m + 1]) for m in range(L // 2)]
+    tail = s[L - 1] if L % 2 else None
+    assert np.max(np.abs(O.pair_product_state(pairs, tail) - O.product_state(s))) < 1e-15
+
+
+def test_paper_model_floquet_unitary_and_initial_energy():
+    """U_F = exp(-i H_o T) exp(-i H_e T) (Sec. III B), the initial energy of the
+    ground state of H_o (Eq. (9)) from single-site reduced states, and pure
+    odd-k bond states."""
+    assert abs(O.paper_model(fin.gue_bond_sample(4), 6.0)[1] - 2 * np.pi / 6.0) < 1e-15
+    assert pins.paper_model_error(O, 6, 6.0) < 1e-12
+    assert pins.paper_model_error(O, 7, 5.0) < 1e-12
 
 
 def test_inputs_first_entries_of_one_long_list():
@@ -300,3 +332,15 @@ def test_infidelity_and_overlap_error_special_cases():
     assert abs(O.infidelity(b, (b + c) / np.sqrt(2)) - 0.5) < 1e-15
     assert O.overlap_error(a, a) < 1e-15
     assert abs(O.overlap_error(a, np.exp(0.1j) * a) - abs(1 - np.exp(0.1j))) < 1e-15
+
+
+def test_planted_swapped_pair_index_is_caught():
+    def pair_product_state(pairs, tail=None):
+        return O.pair_product_state([np.asarray(d).reshape(2, 2).T.reshape(4) for d in pairs], tail)
+    assert pins.paper_model_error(_mutant(pair_product_state=pair_product_state), 6, 6.0) > 1e-3
+
+
+def test_planted_full_strength_paper_gate_is_caught():
+    def paper_model(Hk, omega):
+        return [np.asarray(H, dtype=np.complex128) for H in Hk], 2.0 * np.pi / omega
+    assert pins.paper_model_error(_mutant(paper_model=paper_model), 6, 6.0) > 1e-3
