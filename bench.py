@@ -287,11 +287,15 @@ def gue_study(fl, torch, L, omegas, tmax, nrec=240):
                           "sigma": [round(x, 6) for x in S_s]}}
         print(json.dumps({k: v for k, v in row.items() if k != "series"}), file=sys.stderr, flush=True)
         out.append(row)
-    fit_rows = [r for r in out if r["gamma"] is not None]
-    fit = None
-    if len(fit_rows) >= 2:
-        a, b = fl.fit_exponential_rate([r["omega"] for r in fit_rows], [r["gamma"] for r in fit_rows])
-        fit = {"a": a, "b": b, "omegas": [r["omega"] for r in fit_rows]}
+    def fit_over(rows):
+        rows = [r for r in rows if r["gamma"] is not None]
+        if len(rows) < 2:
+            return None
+        a, b = fl.fit_exponential_rate([r["omega"] for r in rows], [r["gamma"] for r in rows])
+        return {"a": a, "b": b, "omegas": [r["omega"] for r in rows]}
+
+    # the paper's fit leaves out the two lowest frequencies (early heating)
+    fit = {"all": fit_over(out), "without_two_lowest": fit_over(sorted(out, key=lambda r: r["omega"])[2:])}
     # infinite-temperature spread: tr(H-bar^2) / 2^L = sum_k |H_k|_F^2 / 4
     # + 2 sum_k tr(R_k L_{k+1}) / 8 (R_k, L_k: H_k traced over its left / right
     # site; terms further apart vanish because every H_k is traceless)
