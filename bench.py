@@ -79,6 +79,8 @@ def parse():
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
                          "or heating of the paper's GUE circuit versus drive frequency (gue)")
     ap.add_argument("--max-periods", type=int, default=10000)
+    ap.add_argument("--variants", type=str, default="plain,dense6_fp32,dense6_bf16x3",
+                    help="complex64 variants of --study precision")
     ap.add_argument("--omegas", type=str, default="5,5.5,6,6.5,7,7.5,8",
                     help="drive frequencies of --study gue")
     ap.add_argument("--tmax", type=float, default=2e5, help="longest time (units of 1/J) of --study gue")
@@ -174,7 +176,7 @@ def _depths(nmax):
     return out
 
 
-def precision_study(fl, torch, L, nmax):
+def precision_study(fl, torch, L, nmax, variants=("plain", "dense6_fp32", "dense6_bf16x3")):
     """Infidelity 1 - |<psi64|psi>|^2/(|psi64|^2 |psi|^2), energy-density error
     |e - e64| and norm drift of the complex64 variants (plain FP32 sweep, FP32
     MFMA windows, split-BF16x3 MFMA windows) against an FP64 GPU run, at
@@ -187,7 +189,7 @@ def precision_study(fl, torch, L, nmax):
     p64 = ref.new_state()
     ref.init(p64, w["spinors"])
     engines, states = {}, {}
-    for var in ("plain", "dense6_fp32", "dense6_bf16x3"):
+    for var in variants:
         e = fl.FloquetEngine(L, "c64", var)
         e.set_bonds(h, w["T"])
         engines[var] = e
@@ -353,7 +355,7 @@ def main():
     L, m = args.L, args.periods_per_step
     torch.cuda.set_device(0)
     if args.study == "precision":
-        print(json.dumps(precision_study(fl, torch, L, args.max_periods)), flush=True)
+        print(json.dumps(precision_study(fl, torch, L, args.max_periods, args.variants.split(","))), flush=True)
         return
     if args.study == "echo":
         print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
