@@ -1070,7 +1070,7 @@ __device__ __forceinline__ void adj_op(T (&pr)[1 << R], T (&pi)[1 << R], T (&lr)
 }
 
 template <typename T, int R, int KT, int KMAX>
-__global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint(typename CT<T>::c* __restrict__ psi,
+__global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_adjoint(typename CT<T>::c* __restrict__ psi,
                                                    typename CT<T>::c* __restrict__ lam, const T* __restrict__ gates,
                                                    int C, int W, uint32_t ntiles, fl_pass pd,
                                                    double* __restrict__ Mpart, int nbonds) {

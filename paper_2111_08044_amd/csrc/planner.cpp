@@ -126,6 +126,31 @@ std::vector<Gate> pack_groups(const fl_geom& g, std::vector<Gate> rem, fl_pass& 
     return rem;
 }
 
+// Passes the plain greedy rule (the window admitting the most gates) needs to
+// finish the circuit from state s.
+int greedy_passes(const fl_geom& g, const std::vector<int>& windows, Sched s, int cap) {
+    long long left = 0;
+    for (int b = 0; b < s.nb; ++b) left += s.n - s.cnt[b];
+    int passes = 0;
+    while (left > 0) {
+        int best = 0;
+        Sched best_s;
+        for (int h : windows) {
+            Sched t = s;
+            const int got = (int)run_tile(g, h, t, cap).size();
+            if (got > best) {
+                best = got;
+                best_s = std::move(t);
+            }
+        }
+        if (best == 0) return 1 << 20;   // cannot happen for a valid circuit
+        s = std::move(best_s);
+        left -= best;
+        ++passes;
+    }
+    return passes;
+}
+
 }  // namespace
 
 std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_slots,
@@ -150,12 +175,18 @@ std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_
 
     long long total = (long long)n * nb, done = 0;
     while (done < total) {
-        int best_h = -1;
+        // One-step lookahead: take the window after which the greedy rule
+        // finishes in the fewest passes; ties go to the window that applies
+        // more gates now, then to the lower window.
+        int best_h = -1, best_cost = 1 << 30;
         std::vector<int> best;
         for (int h : windows) {
             Sched t = s;
             std::vector<int> got = run_tile(g, h, t, max_gates_per_pass);
-            if (got.size() > best.size()) {
+            if (got.empty()) continue;
+            const int cost = greedy_passes(g, windows, t, max_gates_per_pass);
+            if (cost < best_cost || (cost == best_cost && got.size() > best.size())) {
+                best_cost = cost;
                 best = got;
                 best_h = h;
             }
