@@ -65,6 +65,8 @@ struct fl_pass {
 
 #ifdef __cplusplus
 // Kernels read the per-op arrays as aligned 32-bit words (scalar loads).
+static_assert(offsetof(fl_pass, u0) % 4 == 0 && sizeof(((fl_pass*)0)->u0) % 4 == 0, "u0 not word aligned");
+static_assert(offsetof(fl_pass, nops) % 4 == 0 && sizeof(((fl_pass*)0)->nops) % 4 == 0, "nops not word aligned");
 static_assert(offsetof(fl_pass, opi) % 4 == 0 && sizeof(((fl_pass*)0)->opi[0]) % 4 == 0, "opi rows not word aligned");
 static_assert(offsetof(fl_pass, opg) % 4 == 0 && sizeof(((fl_pass*)0)->opg[0]) % 4 == 0, "opg rows not word aligned");
 static_assert(offsetof(fl_pass, ops) % 4 == 0 && sizeof(((fl_pass*)0)->ops[0]) % 4 == 0, "ops rows not word aligned");

@@ -331,6 +331,12 @@ __device__ __forceinline__ int pass_slot(const fl_pass& pd, int g, int q) {
     const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.ops[g][0])[q >> 1];
     return (q & 1) ? (w >> 16) : (int)(int16_t)(w & 0xffff);
 }
+__device__ __forceinline__ int pass_byte(const int8_t* row, int i) {
+    const int32_t w = reinterpret_cast<const fl_i32a*>(row)[i >> 2];
+    return (int)(int8_t)((w >> (8 * (i & 3))) & 0xff);
+}
+__device__ __forceinline__ int pass_u0(const fl_pass& pd, int g) { return pass_byte(pd.u0, g); }
+__device__ __forceinline__ int pass_nops(const fl_pass& pd, int g) { return pass_byte(pd.nops, g); }
 __device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
     const int32_t w = reinterpret_cast<const fl_i32a*>(&pd.opi[g][0])[q >> 2];
     return (w >> (8 * (q & 3))) & 0xff;
@@ -372,8 +378,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     // LDS slot of element j + s APL NT is fl_swz(j) + s APL NT (the swizzle
     // only mixes bits 0..7), and fl_swz(j + 1) = fl_swz(j) ^ 1 for even j.
     const uint32_t l0 = fl_swz(APL * threadIdx.x);
-    const bool din = ng > 0 && pd.u0[0] >= FL_DIRECT_MIN_U0;
-    const bool dout = ng > 0 && pd.u0[ng - 1] >= FL_DIRECT_MIN_U0;
+    const bool din = ng > 0 && pass_u0(pd, 0) >= FL_DIRECT_MIN_U0;
+    const bool dout = ng > 0 && pass_u0(pd, ng - 1) >= FL_DIRECT_MIN_U0;
 
     T vr[SUB][1 << R], vi[SUB][1 << R];
     uint32_t b0[SUB];
@@ -398,19 +404,36 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             if ((m >> k) & 1) r += d[k];
         return r;
     };
-    auto lds_to_regs = [&](int u0) {
+    // LDS byte offsets of the current register group.  The swizzle is linear
+    // over XOR and b0 and m << u0 have disjoint bits, so
+    // slot(b0 | m << u0) = slot(b0) ^ slot(m << u0), and slot(m << u0) is the
+    // XOR of the (uniform) slots of m's set bits: one VALU XOR per element.
+    // Kept for the group's write-back.
+    uint32_t la[SUB][1 << R];
+    auto lds_addrs = [&](int u0) {
+        uint32_t bk[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) bk[k] = fl_swz(1u << (u0 + k)) * (uint32_t)sizeof(cplx);
 #pragma unroll
         for (int s = 0; s < SUB; ++s) {
             b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
+            la[s][0] = fl_swz(b0[s]) * (uint32_t)sizeof(cplx);
+#pragma unroll
+            for (int m = 1; m < (1 << R); ++m) la[s][m] = la[s][m & (m - 1)] ^ bk[__builtin_ctz(m)];
+        }
+    };
+    char* const lbytes = reinterpret_cast<char*>(lds);
+    auto lds_to_regs = [&]() {
+#pragma unroll
+        for (int s = 0; s < SUB; ++s)
 #pragma unroll
             for (int m = 0; m < (1 << R); ++m) {
-                const cplx a = lds[fl_swz(b0[s] | ((uint32_t)m << u0))];
+                const cplx a = *reinterpret_cast<const cplx*>(lbytes + la[s][m]);
                 vr[s][m] = a.x;
                 vi[s][m] = a.y;
             }
-        }
     };
-    auto regs_to_lds = [&](int u0) {
+    auto regs_to_lds = [&]() {
 #pragma unroll
         for (int s = 0; s < SUB; ++s)
 #pragma unroll
@@ -418,13 +441,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
                 cplx a;
                 a.x = vr[s][m];
                 a.y = vi[s][m];
-                lds[fl_swz(b0[s] | ((uint32_t)m << u0))] = a;
+                *reinterpret_cast<cplx*>(lbytes + la[s][m]) = a;
             }
     };
 
     if (din) {
         uint64_t o[SUB], d[R];
-        group_offsets(pd.u0[0], o, d);
+        group_offsets(pass_u0(pd, 0), o, d);
 #pragma unroll
         for (int s = 0; s < SUB; ++s)
 #pragma unroll
@@ -448,13 +471,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             }
         }
         __syncthreads();
-        if (ng > 0) lds_to_regs(pd.u0[0]);
+        if (ng > 0) {
+            lds_addrs(pass_u0(pd, 0));
+            lds_to_regs();
+        }
     }
 
     for (int g = 0; g < ng; ++g) {
-        const int u0 = pd.u0[g];
-        const int nops = pd.nops[g];
-        if (g > 0) lds_to_regs(u0);
+        const int u0 = pass_u0(pd, g);
+        const int nops = pass_nops(pd, g);
+        if (g > 0 || din) lds_addrs(u0);
+        if (g > 0) lds_to_regs();
         // Ops run two per iteration (the register copies that LLVM places on
         // a loop back edge after the 4-way choice of gate bits are then not
         // needed at all).  The next op's gate (32 scalar registers) is fetched
@@ -494,13 +521,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             }
         }
         if (g == ng - 1 && dout) break;
-        regs_to_lds(u0);
+        regs_to_lds();
         __syncthreads();
     }
 
     if (dout) {
         uint64_t o[SUB], d[R];
-        group_offsets(pd.u0[ng - 1], o, d);
+        group_offsets(pass_u0(pd, ng - 1), o, d);
 #pragma unroll
         for (int s = 0; s < SUB; ++s)
 #pragma unroll
@@ -1091,8 +1118,8 @@ __global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T)
         tile_load<T, KT>(lam, base, K, C, h, ll);
         __syncthreads();
         for (int g = 0; g < pd.ngroups; ++g) {
-            const int u0 = pd.u0[g];
-            const int nops = pd.nops[g];
+            const int u0 = pass_u0(pd, g);
+            const int nops = pass_nops(pd, g);
             const uint32_t b0 = fl_spread(active ? threadIdx.x : 0u, u0, R);
             T pr[1 << R], pi[1 << R], lr[1 << R], li[1 << R];
 #pragma unroll
@@ -1198,7 +1225,9 @@ typedef __bf16 fl_bf16x8 __attribute__((ext_vector_type(8)));
 
 #define FL_DENSE_PLANE_STRIDE 136   // bf16 per column of a split plane (128 + 8 pad)
 
-template <int MODE>
+// FULL: the tile has the full KMAXD = 13 bits (every chain with L >= 13), so
+// the column-block and element counts are compile-time constants.
+template <int MODE, bool FULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense6(float2* __restrict__ psi, const float4* __restrict__ mats,
                                                 uint32_t ntiles, int C, int W, fl_pass pd) {
     constexpr int KMAXD = 13;
@@ -1207,18 +1236,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     constexpr int LDS_BYTES = (MODE == 1 && 2 * PLANE_BYTES > TILE_BYTES) ? 2 * PLANE_BYTES : TILE_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
     float2* lds = reinterpret_cast<float2*>(smem);
-    const int K = C + W;
+    const int K = FULL ? KMAXD : C + W;
     const int h = pd.h;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lc = lane & 31, lk = lane >> 5;
-    const int ncb = 1 << (K - 6 - 5);          // 32-column blocks (1, 2 or 4)
+    const int ncb = FULL ? 4 : 1 << (K - 6 - 5);   // 32-column blocks (1, 2 or 4)
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
     tile_load<float, 0>(psi, base, K, C, h, lds);
     __syncthreads();
     for (int g = 0; g < pd.ngroups; ++g) {
-        const int u0 = pd.u0[g];
+        const int u0 = pass_u0(pd, g);
         // 4096 float4 (64 KiB) per window; MODE 1 keeps hi at [0, 2048), lo at [2048, 4096)
-        const float4* M = mats + (size_t)pd.opg[g][0] * 4096 + (size_t)(w * 64 + lane) * (MODE == 0 ? 16 : 8);
+        const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 4096 + (size_t)(w * 64 + lane) * (MODE == 0 ? 16 : 8);
         uint32_t cbase[4];
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) cbase[cb] = fl_spread((32 * cb + lc) & ((1 << (K - 6)) - 1), u0, 6);
@@ -1237,16 +1266,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                 a[4 * q + 2] = t.z;
                 a[4 * q + 3] = t.w;
             }
+            // element (column, m) of the tile sits at slot(cbase | m << u0) =
+            // slot(cbase) ^ slot(m << u0) (the swizzle is linear over XOR); the
+            // lane's half (re for lk = 0, im for lk = 1) is 4 lk bytes further
+            uint32_t bb[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bb[cb] = fl_swz(cbase[cb]) * 8u + 4u * (uint32_t)lk;
+            // B operands of step kk + 2 are read while step kk multiplies
+            constexpr int PF = 2;
+            float bq[PF + 1][4];
+            auto fetch = [&](int kk, float (&dst)[4]) {
+                const uint32_t sk = fl_swz((uint32_t)kk << u0) * 8u;
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    if (cb < ncb) dst[cb] = *reinterpret_cast<const float*>(smem + (bb[cb] ^ sk));
+            };
+#pragma unroll
+            for (int kk = 0; kk < PF; ++kk) fetch(kk, bq[kk]);
 #pragma unroll
             for (int kk = 0; kk < 64; ++kk) {
+                if (kk + PF < 64) fetch(kk + PF, bq[(kk + PF) % (PF + 1)]);
 #pragma unroll
-                for (int cb = 0; cb < 4; ++cb) {
-                    if (cb < ncb) {
-                        const float2 v = lds[fl_swz(cbase[cb] | ((uint32_t)kk << u0))];
-                        const float b = lk ? v.y : v.x;
-                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], b, acc[cb], 0, 0, 0);
-                    }
-                }
+                for (int cb = 0; cb < 4; ++cb)
+                    if (cb < ncb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], bq[kk % (PF + 1)][cb], acc[cb], 0, 0, 0);
             }
             __syncthreads();
         } else {
@@ -1255,7 +1298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             // the planes overwrite the FP32 tile in LDS)
             constexpr int PER = (1 << KMAXD) / 256;
             float2 mine[PER];
-            const int nper = (1 << K) / 256;
+            const int nper = FULL ? PER : (1 << K) / 256;
             const uint32_t l0 = fl_swz(threadIdx.x);   // fl_swz(tid + 256 t) = l0 + 256 t
 #pragma unroll
             for (int t = 0; t < PER; ++t)
@@ -1263,21 +1306,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             __syncthreads();
             __bf16* ph = reinterpret_cast<__bf16*>(smem);
             __bf16* pl = ph + 128 * FL_DENSE_PLANE_STRIDE;
+            // plane offset o(j) = col(j) * STRIDE + 2 m(j) of element j: col and m
+            // are bit fields of j, so o(tid | t << 8) = o(tid) + o(t << 8), the
+            // second term uniform
+            auto plane_off = [&](uint32_t j) {
+                const uint32_t m = (j >> u0) & 63;
+                const uint32_t col = (j & ((1u << u0) - 1)) | ((j >> (u0 + 6)) << u0);
+                return col * FL_DENSE_PLANE_STRIDE + 2 * m;
+            };
+            const uint32_t otid = plane_off(threadIdx.x);
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
                 if (t < nper) {
-                    const uint32_t j = threadIdx.x + 256 * t;
-                    const uint32_t m = (j >> u0) & 63;
-                    const uint32_t lo_bits = j & ((1u << u0) - 1);
-                    const uint32_t col = lo_bits | ((j >> (u0 + 6)) << u0);
                     const float2 x = mine[t];
-                    const __bf16 hr = (__bf16)x.x, hi_ = (__bf16)x.y;
-                    const __bf16 lr = (__bf16)(x.x - (float)hr), li = (__bf16)(x.y - (float)hi_);
-                    const uint32_t o = col * FL_DENSE_PLANE_STRIDE + 2 * m;
-                    ph[o] = hr;
-                    ph[o + 1] = hi_;
-                    pl[o] = lr;
-                    pl[o + 1] = li;
+                    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+                    bf2 hv, lv;
+                    hv.x = (__bf16)x.x;
+                    hv.y = (__bf16)x.y;
+                    lv.x = (__bf16)(x.x - (float)hv.x);
+                    lv.y = (__bf16)(x.y - (float)hv.y);
+                    // (re, im) of one amplitude are adjacent in a plane: one
+                    // 32-bit LDS store per plane
+                    // readfirstlane: keep the uniform term a scalar (otherwise the
+                    // two products get refactored into one vector multiply)
+                    const uint32_t o = otid + __builtin_amdgcn_readfirstlane(plane_off(256u * (uint32_t)t));
+                    *reinterpret_cast<bf2*>(ph + o) = hv;
+                    *reinterpret_cast<bf2*>(pl + o) = lv;
                 }
             }
             // A fragments are loaded after the split so that the two never
@@ -1310,19 +1364,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
         // write Y back to the FP32 tile: register r of block cb holds row
         // 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column 32 cb + lc
+        // (slots as above: slot(cbase) ^ slot(m << u0), the second part uniform)
+        const uint32_t mrow = 16 * w + 2 * lk;   // m of register 0 (rows 32w + 4lk, +1)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             if (cb < ncb) {
+                const uint32_t vb = fl_swz(cbase[cb]) * 8u;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row0 = 32 * w + 8 * q + 4 * lk;     // even: rows row0..row0+3 = 2 amplitudes
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
-                        const uint32_t m = (row0 >> 1) + p;
+                        const uint32_t m = mrow + 4 * q + p;   // rows 32w + 8q + 4lk + 2p, +1
                         float2 v;
                         v.x = acc[cb][4 * q + 2 * p];
                         v.y = acc[cb][4 * q + 2 * p + 1];
-                        lds[fl_swz(cbase[cb] | (m << u0))] = v;
+                        *reinterpret_cast<float2*>(smem + (vb ^ (fl_swz(m << u0) * 8u))) = v;
                     }
                 }
             }
@@ -1507,12 +1563,19 @@ hipError_t launch_zero(double* p, uint64_t n, hipStream_t s) {
 
 hipError_t launch_dense6(int mode, const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s) {
     const uint32_t nt = ntiles_of(g);
-    if (mode == 0)
-        hipLaunchKernelGGL(k_dense6<0>, dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C, g.W,
-                           pd);
+    const bool full = g.C + g.W == 13;
+    if (mode == 0 && full)
+        hipLaunchKernelGGL((k_dense6<0, true>), dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C,
+                           g.W, pd);
+    else if (mode == 0)
+        hipLaunchKernelGGL((k_dense6<0, false>), dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C,
+                           g.W, pd);
+    else if (full)
+        hipLaunchKernelGGL((k_dense6<1, true>), dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C,
+                           g.W, pd);
     else
-        hipLaunchKernelGGL(k_dense6<1>, dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C, g.W,
-                           pd);
+        hipLaunchKernelGGL((k_dense6<1, false>), dim3(nt), dim3(256), 0, s, (float2*)psi, (const float4*)mats, nt, g.C,
+                           g.W, pd);
     return hipGetLastError();
 }
 
