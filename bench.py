@@ -196,19 +196,23 @@ def precision_study(fl, torch, L, nmax, variants=("plain", "dense6_fp32", "dense
         states[var] = e.new_state()
         e.init(states[var], w["spinors"])
     rows, t, times = [], 0, {k: 0.0 for k in ["c128"] + list(engines)}
+    chunk = 500
     for d in _depths(nmax):
-        k = d - t
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ref.step(p64, k)
-        torch.cuda.synchronize()
-        times["c128"] += time.perf_counter() - t0
-        for var, e in engines.items():
-            t0 = time.perf_counter()
-            e.step(states[var], k)
+        while t < d:
+            k = min(chunk, d - t)
             torch.cuda.synchronize()
-            times[var] += time.perf_counter() - t0
-        t = d
+            t0 = time.perf_counter()
+            ref.step(p64, k)
+            torch.cuda.synchronize()
+            times["c128"] += time.perf_counter() - t0
+            for var, e in engines.items():
+                t0 = time.perf_counter()
+                e.step(states[var], k)
+                torch.cuda.synchronize()
+                times[var] += time.perf_counter() - t0
+            t += k
+            if t < d:
+                print(json.dumps({"periods_done": t}), file=sys.stderr, flush=True)
         E64, N64 = ref.energy(p64)
         row = {"period": d, "e64": E64 / (L * N64), "norm64_minus_1": N64 - 1.0}
         for var, e in engines.items():

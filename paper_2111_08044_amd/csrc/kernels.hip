@@ -790,24 +790,41 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
         nrm += (double)tn;
         __syncthreads();
         for (int g = 0; g < pd.ngroups; ++g) {
-            const int u = pd.u0[g];
+            const int u = pass_u0(pd, g);
             T r[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) r[k] = 0;
-#pragma unroll 2
-            for (int s = 0; s < (1 << (K - 2)) / NT; ++s) {
-                const uint32_t b0 = fl_spread(threadIdx.x + s * NT, u, 2);
+            // slot(spread(tid + NT s) | l << u) = slot(spread(tid)) ^ slot(spread(NT s)) ^ slot(l << u)
+            // (the swizzle is linear over XOR; the three parts have disjoint
+            // bits), the last two uniform: one VALU XOR per read
+            const uint32_t vb = fl_swz(fl_spread(threadIdx.x, u, 2)) * (uint32_t)sizeof(cplx);
+            constexpr int NS = (1 << (K - 2)) / NT;
+            // all reads of the group first, so that their latencies overlap
+            cplx q[NS][4];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const uint32_t us = fl_swz(fl_spread((uint32_t)(s * NT), u, 2)) * (uint32_t)sizeof(cplx);
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const uint32_t ul = us ^ (fl_swz((uint32_t)l << u) * (uint32_t)sizeof(cplx));
+                    q[s][l] = *reinterpret_cast<const cplx*>(reinterpret_cast<const char*>(lds) + (vb ^ ul));
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
                 T ar[4], ai[4];
 #pragma unroll
                 for (int l = 0; l < 4; ++l) {
-                    const cplx a = lds[fl_swz(b0 | ((uint32_t)l << u))];
-                    ar[l] = a.x;
-                    ai[l] = a.y;
+                    ar[l] = q[s][l].x;
+                    ai[l] = q[s][l].y;
                 }
                 rdm_quad<T>(ar, ai, r);
             }
+            // lane l holds the sum of value l >> 2; one lane of each four adds
+            // it, the others add zero (an LDS atomic with every lane active)
             const T red = wave_transpose_reduce<T, 16>(r);
-            if ((lane & 3) == 0) wacc[wave][g][lane >> 2] += (double)red;
+            __hip_atomic_fetch_add(&wacc[wave][g][lane >> 2], (lane & 3) == 0 ? (double)red : 0.0, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     double nv[1] = {nrm};
