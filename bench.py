@@ -96,9 +96,16 @@ def plan_passes(fl, L, n):
     return int(fl.fl_plan_query(L, "c64", 0, n, False)[3])
 
 
-def _dense_groups(fl, L, n):
-    """Register groups (= windows) of each pass of the dense plan for n periods."""
-    words = [int(x) for x in fl.fl_plan_query(L, "c64", 4, n, False)]
+DENSE = {  # plan kind, MFMA flop per amplitude per window, MFMA peak (TFLOP/s, dense)
+    "dense6_fp32": (4, 512.0, 157.3),
+    "dense6_bf16x3": (4, 1536.0, 2516.6),
+    "dense4_fp32": (5, 128.0, 157.3),
+}
+
+
+def _dense_groups(fl, L, n, kind=4):
+    """Register groups (= windows) of each pass of a dense plan for n periods."""
+    words = [int(x) for x in fl.fl_plan_query(L, "c64", kind, n, False)]
     npasses, i, out = words[3], 4, []
     for _ in range(npasses):
         ng = words[i + 1]
@@ -435,7 +442,7 @@ def main():
     }
     # ---- the same step through the dense 6-qubit windows on the matrix cores
     variants = {}
-    for var in ("dense6_fp32", "dense6_bf16x3"):
+    for var in DENSE:
         ev = fl.FloquetEngine(L, "c64", var)
         ev.set_xyz(w["J"], w["fields"], w["T"])
         ev.init(psi, w["spinors"])
@@ -446,11 +453,12 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / (nblk * reps)
-        nwin = sum(len(g) for g in _dense_groups(fl, L, nblk)) * reps
-        mflop = (512.0 if var == "dense6_fp32" else 1536.0) * (1 << L) * nwin / (ev0.elapsed_time(ev1) / 1e3) / 1e12
+        kind, fpa, mpeak = DENSE[var]
+        nwin = sum(len(g) for g in _dense_groups(fl, L, nblk, kind)) * reps
+        mflop = fpa * (1 << L) * nwin / (ev0.elapsed_time(ev1) / 1e3) / 1e12
         variants[var] = {"ms_per_period": round(ms, 3), "periods_per_s": round(1e3 / ms, 2),
                          "windows_per_period": nwin / (nblk * reps), "mfma_tflops": round(mflop, 2),
-                         "mfma_peak": 157.3 if var == "dense6_fp32" else 2516.6,
+                         "mfma_peak": mpeak,
                          "energy_density_after_" + str(nblk * (reps + 1)): ev.energy_density(psi)}
         del ev
     out["dense_variants"] = variants

@@ -62,6 +62,7 @@ extern "C" {
 #define FL_PLAIN 0           /* fused 4x4 gate sweep on the vector ALUs */
 #define FL_DENSE6_FP32 1     /* 6-qubit windows pre-multiplied, FP32 MFMA (complex64 only) */
 #define FL_DENSE6_BF16X3 2   /* 6-qubit windows pre-multiplied, split-BF16x3 MFMA, FP32 accumulation */
+#define FL_DENSE4_FP32 3     /* 4-qubit windows pre-multiplied, FP32 MFMA (complex64, L >= 13) */
 
 typedef struct fl_ctx fl_ctx;
 
@@ -185,17 +186,21 @@ int fl_xyz_generators(int L, double *gens_out);
  * Returns FL_EINVAL for L > 24 or an invalid window. */
 int fl_tile_map(int L, int dtype, int h, uint64_t *out);
 
-/* The 64x64 window matrix a dense plan applies for one register group:
+/* The window matrix a dense plan applies for one register group:
  * U = E(op_{n-1}) ... E(op_0), E(op_k) = the 4x4 gate G[k] ([nops][4][4]
  * complex) embedded at window bits (pos[k], pos[k]+1), window index bit i =
- * tile bit u0 + i, gate local index 2*bit(pos+1) + bit(pos).  U_out:
- * [64][64] complex.  If frag_out is not NULL it receives the 64 KiB of MFMA
- * fragments of the real 128x128 form for mode 0 (FP32) or 1 (bf16 hi/lo). */
+ * tile bit u0 + i, gate local index 2*bit(pos+1) + bit(pos).
+ * mode -1, 0, 1: 6-bit window, U_out [64][64] complex; if frag_out is not
+ * NULL it receives the 64 KiB of MFMA fragments of the real 128x128 form for
+ * mode 0 (FP32) or 1 (bf16 hi/lo).  mode 2: 4-bit window, U_out [16][16]
+ * complex, frag_out (if not NULL) the 4 KiB of FP32 fragments of the real
+ * 32x32 form. */
 int fl_host_window_matrix(const double *G, const int *pos, int nops, int mode, double *U_out, void *frag_out);
 
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
  * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover,
- * 3 = cover used for H0 psi, 4 = dense 6-qubit-window sweep), flattened as int32:
+ * 3 = cover used for H0 psi, 4 = dense 6-qubit-window sweep, 5 = dense
+ * 4-qubit-window sweep), flattened as int32:
  * [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {i, gate, slot}*}*}*].
  * Writes at most cap words to buf (may be NULL) and the required count to
  * *needed. */

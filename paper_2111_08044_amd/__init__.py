@@ -19,7 +19,7 @@ import ctypes as C
 import numpy as np
 
 from . import _native
-from ._native import (FL_C64, FL_C128, FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X3,  # noqa: F401
+from ._native import (FL_C64, FL_C128, FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X3, FL_DENSE4_FP32,  # noqa: F401
                       FloquetError, check, lib)
 
 __all__ = [
@@ -32,7 +32,8 @@ __all__ = [
 ]
 
 _DTYPES = {"c64": FL_C64, "c128": FL_C128}
-_VARIANTS = {"plain": FL_PLAIN, "dense6_fp32": FL_DENSE6_FP32, "dense6_bf16x3": FL_DENSE6_BF16X3}
+_VARIANTS = {"plain": FL_PLAIN, "dense6_fp32": FL_DENSE6_FP32, "dense6_bf16x3": FL_DENSE6_BF16X3,
+             "dense4_fp32": FL_DENSE4_FP32}
 
 
 def _dp(a: np.ndarray):
@@ -243,14 +244,16 @@ def fl_host_ground_states(h):
 
 
 def fl_host_window_matrix(G, pos, mode=None):
-    """(U, fragments) of a dense window: U = E(op_n-1)...E(op_0) (64x64) and, for
-    mode 0/1, the 64 KiB of MFMA fragments as raw bytes."""
+    """(U, fragments) of a dense window: U = E(op_n-1)...E(op_0) and, for mode
+    0/1 (6-bit window, U 64x64), the 64 KiB of MFMA fragments as raw bytes;
+    mode 2: 4-bit window, U 16x16, 4 KiB of FP32 fragments."""
     G = np.asarray(G, dtype=np.complex128)
     n = G.shape[0]
     Gb = _c16(G, (n, 4, 4))
     p = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
-    U = np.zeros((64, 64), dtype=np.complex128)
-    frag = np.zeros(65536, dtype=np.uint8) if mode is not None else None
+    dim = 16 if mode == 2 else 64
+    U = np.zeros((dim, dim), dtype=np.complex128)
+    frag = np.zeros(4096 if mode == 2 else 65536, dtype=np.uint8) if mode is not None else None
     check(lib().fl_host_window_matrix(_dp(Gb), p.ctypes.data_as(C.POINTER(C.c_int)), n,
                                       -1 if mode is None else int(mode), _dp(U.view(np.float64)),
                                       frag.ctypes.data_as(C.c_void_p) if frag is not None else None))

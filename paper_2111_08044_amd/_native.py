@@ -12,7 +12,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfloquet.
 
 FL_OK, FL_EINVAL, FL_ENOMEM, FL_EHIP, FL_ESTATE, FL_ENODEV = 0, -1, -2, -3, -4, -5
 FL_C64, FL_C128 = 0, 1
-FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X3 = 0, 1, 2
+FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X3, FL_DENSE4_FP32 = 0, 1, 2, 3
 
 _ERRNAMES = {FL_EINVAL: "FL_EINVAL", FL_ENOMEM: "FL_ENOMEM", FL_EHIP: "FL_EHIP",
              FL_ESTATE: "FL_ESTATE", FL_ENODEV: "FL_ENODEV"}

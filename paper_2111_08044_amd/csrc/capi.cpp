@@ -189,7 +189,9 @@ int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
     return FL_OK;
 }
 
-bool is_dense(const fl_ctx* c) { return c->variant == FL_DENSE6_FP32 || c->variant == FL_DENSE6_BF16X3; }
+bool is_dense(const fl_ctx* c) {
+    return c->variant == FL_DENSE6_FP32 || c->variant == FL_DENSE6_BF16X3 || c->variant == FL_DENSE4_FP32;
+}
 
 // Fuse every register group of a 6-bit-window plan into its 64x64 matrix
 // (FP64 product of the embedded gates) and upload the MFMA fragments.
@@ -204,8 +206,10 @@ int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
     std::vector<fl_pass> plan = fl::plan_sweep(c->geom, n, dagger, false, kMaxGatesPerPass);
     size_t nwin = 0;
     for (const fl_pass& p : plan) nwin += p.ngroups;
+    const bool d4 = c->variant == FL_DENSE4_FP32;
     const int mode = c->variant == FL_DENSE6_FP32 ? 0 : 1;
-    std::vector<unsigned char> frags(nwin * 65536);
+    const size_t fbytes = d4 ? 4096 : 65536;   // fragments per window
+    std::vector<unsigned char> frags(nwin * fbytes);
     std::vector<cd> U(64 * 64);
     std::vector<cd> Gd((size_t)nb * 16);
     for (int b = 0; b < nb; ++b)
@@ -221,8 +225,13 @@ int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
                 gates[k] = gi < nb ? &c->G[(size_t)gi * 16] : &Gd[(size_t)(gi - nb) * 16];
                 pos[k] = p.opi[g][k];
             }
-            fl::window_matrix(gates, pos, p.nops[g], U.data());
-            fl::window_fragments(U.data(), mode, frags.data() + w * 65536);
+            if (d4) {
+                fl::window_matrix_bits(gates, pos, p.nops[g], 4, U.data());
+                fl::window_fragments4(U.data(), reinterpret_cast<float*>(frags.data() + w * fbytes));
+            } else {
+                fl::window_matrix(gates, pos, p.nops[g], U.data());
+                fl::window_fragments(U.data(), mode, frags.data() + w * fbytes);
+            }
             p.nops[g] = 1;
             p.opi[g][0] = 0;
             p.opg[g][0] = (int16_t)w;
@@ -254,8 +263,9 @@ int run_dense(fl_ctx* c, void* psi, int64_t n, bool dagger) {
         int rc = build_dense_plan(c, m, dagger, &dp);
         if (rc) return rc;
         for (const fl_pass& p : dp->passes) {
-            hipError_t e = fl::launch_dense6(mode, c->geom, psi, dp->d_mats, p, c->stream);
-            if (e != hipSuccess) return fail_hip(e, "k_dense6 launch");
+            hipError_t e = c->variant == FL_DENSE4_FP32 ? fl::launch_dense4(c->geom, psi, dp->d_mats, p, c->stream)
+                                                         : fl::launch_dense6(mode, c->geom, psi, dp->d_mats, p, c->stream);
+            if (e != hipSuccess) return fail_hip(e, "dense window kernel launch");
         }
         return FL_OK;
     };
@@ -329,8 +339,10 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "dtype must be FL_C64 or FL_C128");
     const int lmax = dtype == FL_C64 ? 34 : 33;
     if (L < 2 || L > lmax) return fail(FL_EINVAL, "L out of range [2, " + std::to_string(lmax) + "]");
-    if (variant != FL_PLAIN && variant != FL_DENSE6_FP32 && variant != FL_DENSE6_BF16X3)
+    if (variant != FL_PLAIN && variant != FL_DENSE6_FP32 && variant != FL_DENSE6_BF16X3 && variant != FL_DENSE4_FP32)
         return fail(FL_EINVAL, "unknown variant");
+    if (variant == FL_DENSE4_FP32 && L < FL_KMAX_C64)
+        return fail(FL_EINVAL, "the 4-qubit-window variant needs full 13-bit tiles (L >= 13)");
     if (variant != FL_PLAIN && (dtype != FL_C64 || L < 11))
         return fail(FL_EINVAL, "dense 6-qubit windows need complex64 and L >= 11");
     int ndev = 0;
@@ -350,8 +362,9 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->variant = variant;
     c->dev = dev;
     c->stream = (hipStream_t)hip_stream;
-    c->geom = (variant == FL_PLAIN) ? fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4)
-                                    : fl::make_geom(L, FL_KMAX_C64, 6);
+    c->geom = (variant == FL_PLAIN)         ? fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4)
+              : (variant == FL_DENSE4_FP32) ? fl::make_geom(L, FL_KMAX_C64, 4)
+                                            : fl::make_geom(L, FL_KMAX_C64, 6);
     c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4);
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
@@ -801,22 +814,25 @@ int fl_tile_map(int L, int dtype, int h, uint64_t* out) {
 
 int fl_host_window_matrix(const double* G, const int* pos, int nops, int mode, double* U_out, void* frag_out) {
     if (!G || !pos || nops < 0 || nops > 64 || !U_out) return fail(FL_EINVAL, "bad argument");
+    if (mode < -1 || mode > 2) return fail(FL_EINVAL, "mode must be -1, 0, 1 or 2");
+    const int nbits = mode == 2 ? 4 : 6, n = 1 << nbits;
     std::vector<cd> g((size_t)nops * 16);
     std::vector<const cd*> gp(nops);
     for (int k = 0; k < nops; ++k) {
-        if (pos[k] < 0 || pos[k] > 4) return fail(FL_EINVAL, "gate position out of the 6-bit window");
+        if (pos[k] < 0 || pos[k] > nbits - 2) return fail(FL_EINVAL, "gate position out of the window");
         read_c16(G + (size_t)k * 32, &g[(size_t)k * 16]);
         gp[k] = &g[(size_t)k * 16];
     }
-    std::vector<cd> U(64 * 64);
-    fl::window_matrix(gp.data(), pos, nops, U.data());
-    for (int i = 0; i < 64 * 64; ++i) {
+    std::vector<cd> U((size_t)n * n);
+    fl::window_matrix_bits(gp.data(), pos, nops, nbits, U.data());
+    for (int i = 0; i < n * n; ++i) {
         U_out[2 * i] = U[i].real();
         U_out[2 * i + 1] = U[i].imag();
     }
     if (frag_out) {
-        if (mode != 0 && mode != 1) return fail(FL_EINVAL, "mode must be 0 or 1");
-        fl::window_fragments(U.data(), mode, frag_out);
+        if (mode == 2) fl::window_fragments4(U.data(), static_cast<float*>(frag_out));
+        else if (mode == 0 || mode == 1) fl::window_fragments(U.data(), mode, frag_out);
+        else return fail(FL_EINVAL, "fragments need mode 0, 1 or 2");
     }
     return FL_OK;
 }
@@ -847,9 +863,10 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     } else if (kind == 2) {
         g = fl::make_geom(L, FL_KMAX_RDM, 2);
         plan = fl::plan_cover(g);
-    } else if (kind == 4) {
-        if (dtype != FL_C64 || L < 11) return fail(FL_EINVAL, "dense plans need complex64 and L >= 11");
-        g = fl::make_geom(L, FL_KMAX_C64, 6);
+    } else if (kind == 4 || kind == 5) {
+        if (dtype != FL_C64 || L < (kind == 4 ? 11 : FL_KMAX_C64))
+            return fail(FL_EINVAL, "dense plans need complex64 and L >= 11 (6-qubit) or 13 (4-qubit windows)");
+        g = fl::make_geom(L, FL_KMAX_C64, kind == 4 ? 6 : 4);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
         if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
@@ -860,7 +877,7 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
         g = fl::make_geom(L, kmax_of(dtype), 4);
         plan = fl::plan_cover(g);
     } else {
-        return fail(FL_EINVAL, "kind must be 0..4");
+        return fail(FL_EINVAL, "kind must be 0..5");
     }
     std::vector<int> words;
     fl::serialize_plan(g, plan, words);

@@ -185,14 +185,32 @@ void embed_gate(const cd* G, int nbits, int i, cd* U) {
     }
 }
 
-void window_matrix(const cd* const* gates, const int* pos, int nops, cd* U) {
-    const int n = 64;
+void window_matrix_bits(const cd* const* gates, const int* pos, int nops, int nbits, cd* U) {
+    const int n = 1 << nbits;
     std::vector<cd> E((size_t)n * n);
     for (int r = 0; r < n * n; ++r) U[r] = (r % (n + 1) == 0) ? cd(1.0) : cd(0.0);
     for (int k = 0; k < nops; ++k) {
-        embed_gate(gates[k], 6, pos[k], E.data());
+        embed_gate(gates[k], nbits, pos[k], E.data());
         mat_mul_n(E.data(), U, U, n);
     }
+}
+
+void window_matrix(const cd* const* gates, const int* pos, int nops, cd* U) {
+    window_matrix_bits(gates, pos, nops, 6, U);
+}
+
+void window_fragments4(const cd* U, float* out) {
+    // real form A[2m'+c'][2m+c] of the 16x16 complex U; lane l, step s holds
+    // A[l % 32][2 s + l / 32]
+    for (int l = 0; l < 64; ++l)
+        for (int st = 0; st < 16; ++st) {
+            const int r = l & 31, k = 2 * st + (l >> 5);
+            const cd u = U[(r >> 1) * 16 + (k >> 1)];
+            double a;
+            if ((r & 1) == 0) a = (k & 1) == 0 ? u.real() : -u.imag();
+            else a = (k & 1) == 0 ? u.imag() : u.real();
+            out[l * 16 + st] = (float)a;
+        }
 }
 
 double bf16_rne(double a) {

@@ -25,9 +25,17 @@ void mat_mul_n(const std::complex<double>* A, const std::complex<double>* B,
 // Embed a 4x4 gate on bits (i, i+1) of an nbits-bit window into a 2^nbits matrix.
 void embed_gate(const std::complex<double>* G, int nbits, int i, std::complex<double>* U);
 
-// U = E(op_{n-1}) ... E(op_0) on a 6-bit window, E = gate gates[k] embedded at
-// window bits (pos[k], pos[k]+1).  U: 64x64 row-major.
+// U = E(op_{n-1}) ... E(op_0) on an nbits-bit window, E = gate gates[k]
+// embedded at window bits (pos[k], pos[k]+1).  U: 2^nbits x 2^nbits row-major.
+void window_matrix_bits(const std::complex<double>* const* gates, const int* pos, int nops, int nbits,
+                        std::complex<double>* U);
+// The 6-bit case (U: 64x64).
 void window_matrix(const std::complex<double>* const* gates, const int* pos, int nops, std::complex<double>* U);
+
+// MFMA fragments of the real 32x32 form of a 16x16 complex window matrix
+// (k = 2m + (0 re, 1 im)): out[lane * 16 + s] = A[lane % 32][2 s + lane / 32],
+// 1024 floats (4 KiB).
+void window_fragments4(const std::complex<double>* U, float* out);
 
 // Round-to-nearest-even to bfloat16 (8 significant bits), returned as a double.
 double bf16_rne(double a);

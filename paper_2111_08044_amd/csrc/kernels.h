@@ -22,6 +22,8 @@ hipError_t launch_apply_h(int dtype, const fl_geom& g, const void* psi, void* la
 hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, const void* gates, const fl_pass& pd,
                           double* Mpart, int grid, hipStream_t s);
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t s);
+// 4-qubit windows on FP32 MFMA; full tiles only (C + W = 13); mats: 4 KiB of fragments per window
+hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s);
 // mode 0: FP32 MFMA, 1: split-BF16x3 MFMA; mats: pre-arranged window matrices of the plan
 hipError_t launch_dense6(int mode, const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s);
 

@@ -1406,6 +1406,87 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // ---------------------------------------------------------------------------
+// dense 4-qubit windows on the FP32 matrix cores (complex64 states)
+// ---------------------------------------------------------------------------
+// Every register group of a dense-4 plan is one window of 4 consecutive tile
+// bits [u0, u0+4); its gates were multiplied on the host (FP64) into a 16x16
+// complex matrix U, applied as the real 32x32 contraction Y = A X with
+// A[2m'+c'][2m+c] = (Re U, -Im U; Im U, Re U)[c'][c] at (m', m): exactly one
+// v_mfma_f32_32x32x2f32 output tile, K = 32 in 16 steps of 2.  Column v of X
+// is the 16-vector of amplitudes sharing the other 9 tile bits; a tile has
+// 512 columns, 128 per wave (4 blocks of 32).  Lane l supplies
+// A[l%32][2s + l/32] (16 VGPRs, the same for every wave) and, per block,
+// X[2s + l/32][32 cb + l%32] = the re (l < 32) or im (l >= 32) part of
+// amplitude s of that column.  A wave reads and writes only its own columns,
+// so each window needs one barrier (before the next window's reads).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense4(float2* __restrict__ psi,
+                                                                                      const float4* __restrict__ mats,
+                                                                                      int W, fl_pass pd) {
+    constexpr int K = 13;
+    constexpr int C = FL_LOWBITS;
+    __shared__ __attribute__((aligned(16))) float2 lds[1 << K];
+    const char* const lbytes = reinterpret_cast<const char*>(lds);
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lc = lane & 31, lk = lane >> 5;
+    const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
+    tile_load<float, K>(psi, base, K, C, h, lds);
+    __syncthreads();
+    for (int g = 0; g < pd.ngroups; ++g) {
+        const int u0 = pass_u0(pd, g);
+        // 64 lanes x 16 floats (4 KiB) per window
+        const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 256 + (size_t)lane * 4;
+        float a[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = M[q];
+            a[4 * q] = t.x;
+            a[4 * q + 1] = t.y;
+            a[4 * q + 2] = t.z;
+            a[4 * q + 3] = t.w;
+        }
+        // slot(spread(col) | s << u0) = slot(spread(col)) ^ slot(s << u0): the
+        // second part is uniform (the swizzle is linear over XOR)
+        uint32_t vb[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+            vb[cb] = fl_swz(fl_spread((uint32_t)(128 * w + 32 * cb + lc), u0, 4)) * 8u;
+        fl_f32x16 acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
+        float bq[16][4];
+#pragma unroll
+        for (int st = 0; st < 16; ++st) {
+            const uint32_t ss = fl_swz((uint32_t)st << u0) * 8u + 4u * (uint32_t)lk;
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb) bq[st][cb] = *reinterpret_cast<const float*>(lbytes + ((vb[cb] ^ ss)));
+        }
+#pragma unroll
+        for (int st = 0; st < 16; ++st)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], bq[st][cb], acc[cb], 0, 0, 0);
+        // register r of block cb holds row 8(r/4) + 4 lk + r%4 = 2m' + c'
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const uint32_t m = 4 * q + 2 * lk + p;
+                    float2 v;
+                    v.x = acc[cb][4 * q + 2 * p];
+                    v.y = acc[cb][4 * q + 2 * p + 1];
+                    *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + (vb[cb] ^ (fl_swz(m << u0) * 8u))) = v;
+                }
+        __syncthreads();
+    }
+    tile_store<float, K>(psi, base, K, C, h, lds);
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 
@@ -1575,6 +1656,12 @@ hipError_t launch_zero(double* p, uint64_t n, hipStream_t s) {
     const uint64_t want = (n + 255) / 256;
     const unsigned grid = (unsigned)(want < 4096 ? (want ? want : 1) : 4096);
     hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s) {
+    if (g.C + g.W != 13 || g.C != FL_LOWBITS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_dense4, dim3(ntiles_of(g)), dim3(256), 0, s, (float2*)psi, (const float4*)mats, g.W, pd);
     return hipGetLastError();
 }
 

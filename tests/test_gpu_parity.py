@@ -409,19 +409,21 @@ def test_abi_error_paths_launch_nothing():
 
 # Per window application, relative L2 error of the state: FP32 MFMA rounds the
 # window matrix and the products to FP32 (a few 2^-24 per entry, summed over
-# 128 terms); split-BF16x3 keeps hi*hi + hi*lo + lo*hi of 8-bit splits, so the
-# dropped lo*lo term and the split residuals are ~3 * 2^-17 relative.
-DENSE_PER_WINDOW = {"dense6_fp32": 2e-6, "dense6_bf16x3": 4e-5}
+# 128 terms for 6-qubit windows, 32 for 4-qubit windows); split-BF16x3 keeps
+# hi*hi + hi*lo + lo*hi of 8-bit splits, so the dropped lo*lo term and the
+# split residuals are ~3 * 2^-17 relative.
+DENSE_PER_WINDOW = {"dense6_fp32": 2e-6, "dense6_bf16x3": 4e-5, "dense4_fp32": 1e-6}
+DENSE_PLAN_KIND = {"dense6_fp32": 4, "dense6_bf16x3": 4, "dense4_fp32": 5}
 
 
-def _windows(L, n, dagger=False):
+def _windows(L, n, dagger=False, variant="dense6_fp32"):
     from tests import plan_tools as pt
-    _, _, _, passes = pt.parse_plan(fl.fl_plan_query(L, "c64", 4, n, dagger))
+    _, _, _, passes = pt.parse_plan(fl.fl_plan_query(L, "c64", DENSE_PLAN_KIND[variant], n, dagger))
     return sum(len(g) for _, _, g in passes)
 
 
-@pytest.mark.parametrize("variant", ["dense6_fp32", "dense6_bf16x3"])
-@pytest.mark.parametrize("L", [11, 12, 13, 14, 16])
+@pytest.mark.parametrize("variant,L", [(v, L) for v in ("dense6_fp32", "dense6_bf16x3") for L in (11, 12, 13, 14, 16)]
+                         + [("dense4_fp32", L) for L in (13, 14, 16)])
 def test_dense_windows_against_oracle(variant, L):
     say(f"case: dense {variant} L={L}")
     w, hs = _model(L, seed=200 + L)
@@ -435,17 +437,17 @@ def test_dense_windows_against_oracle(variant, L):
     for n in (1, 7, 17):
         fl.fl_apply_period(ctx, psi, n)
         ref = O.evolve(ref, L, G, n)
-        napp += _windows(L, n)
+        napp += _windows(L, n, False, variant)
         err = np.linalg.norm(psi.cpu().numpy().astype(np.complex128) - ref)
         say(f"  n={n} windows={napp} L2 err {err:.3e}")
         assert err < napp * DENSE_PER_WINDOW[variant], (n, err)
     fl.fl_apply_period(ctx, psi, 25, dagger=True)
-    napp += _windows(L, 25, True)
+    napp += _windows(L, 25, True, variant)
     err = np.linalg.norm(psi.cpu().numpy().astype(np.complex128) - O.product_state(w["spinors"]))
     assert err < napp * DENSE_PER_WINDOW[variant], err
 
 
-@pytest.mark.parametrize("variant", ["dense6_fp32", "dense6_bf16x3"])
+@pytest.mark.parametrize("variant", ["dense6_fp32", "dense6_bf16x3", "dense4_fp32"])
 def test_dense_L30_lightcone_rdms(variant):
     """L = 30 through the dense windows: bond density matrices after 3 periods
     against the oracle on light-cone subchains."""
@@ -462,7 +464,7 @@ def test_dense_L30_lightcone_rdms(variant):
     worst = 0.0
     for b in (0, 5, 12, 13, 20, 28):
         worst = max(worst, np.max(np.abs(rho[b] - _lightcone_rdm(L, hs, G, w["spinors"], n, b))))
-    napp = _windows(L, n)
+    napp = _windows(L, n, False, variant)
     say(f"dense {variant} L=30: worst rdm err {worst:.3e} over {napp} windows, |N-1| {abs(N - 1):.3e}")
     assert worst < 4 * napp * DENSE_PER_WINDOW[variant]
     del psi

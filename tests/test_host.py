@@ -302,3 +302,45 @@ def test_dense_plan_is_the_brickwork_circuit(L, n, dagger):
     assert R == 6
     seq = pt.gate_sequence(L, words)
     pt.check_trace_equivalent(L, [b for b, _, _ in seq], n, dagger)
+
+
+def _real_form32(U):
+    """Real 32x32 form of a 16x16 complex U, k = 2m + (0 re, 1 im), written out
+    from the definition (Re U, -Im U; Im U, Re U) per 2x2 block."""
+    A = np.zeros((32, 32))
+    A[0::2, 0::2] = U.real
+    A[0::2, 1::2] = -U.imag
+    A[1::2, 0::2] = U.imag
+    A[1::2, 1::2] = U.real
+    return A
+
+
+def test_window4_matrix_and_fragments():
+    """4-bit windows: U is the product of the embedded gates (a 4-site chain,
+    window bit i = site 3 - i) and lane l, step s holds A[l % 32][2 s + l / 32]."""
+    rng = np.random.default_rng(8)
+    G = np.array([np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
+                  for _ in range(5)])
+    pos = [0, 2, 1, 0, 2]
+    U, frag = fl.fl_host_window_matrix(G, pos, 2)
+    ref = np.eye(16, dtype=complex)
+    for g, p in zip(G, pos):
+        ref = O.embed_bond(4, 2 - p, g) @ ref
+    assert U.shape == (16, 16) and np.max(np.abs(U - ref)) < 1e-14
+    A = _real_form32(U)
+    f = frag.view(np.float32).reshape(64, 16).astype(np.float64)
+    l, st = np.meshgrid(np.arange(64), np.arange(16), indexing="ij")
+    assert np.array_equal(f, A[l & 31, 2 * st + (l >> 5)].astype(np.float32).astype(np.float64))
+    with pytest.raises(fl.FloquetError):
+        fl.fl_host_window_matrix(G, [0, 3], 2)   # gate position outside a 4-bit window
+
+
+@pytest.mark.parametrize("L", [13, 16, 30, 34])
+@pytest.mark.parametrize("n", [1, 7, 16, 17])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_dense4_plan_is_the_brickwork_circuit(L, n, dagger):
+    words = fl.fl_plan_query(L, "c64", 5, n, dagger)
+    C, W, R, passes = pt.parse_plan(words)
+    assert R == 4 and C + W == 13
+    seq = pt.gate_sequence(L, words)
+    pt.check_trace_equivalent(L, [b for b, _, _ in seq], n, dagger)
