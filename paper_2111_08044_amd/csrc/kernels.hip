@@ -1660,7 +1660,16 @@ hipError_t launch_zero(double* p, uint64_t n, hipStream_t s) {
 }
 
 hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s) {
-    if (g.C + g.W != 13 || g.C != FL_LOWBITS) return hipErrorInvalidValue;
+    if (g.C + g.W != 13) return hipErrorInvalidValue;
+    if (g.W == 0) {
+        // a single 13-bit tile (L = 13): the same amplitudes as low bits
+        // [0, 6) plus the window [6, 13), the kernel's fixed geometry
+        fl_pass p = pd;
+        p.h = FL_LOWBITS;
+        hipLaunchKernelGGL(k_dense4, dim3(1), dim3(256), 0, s, (float2*)psi, (const float4*)mats, 13 - FL_LOWBITS, p);
+        return hipGetLastError();
+    }
+    if (g.C != FL_LOWBITS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_dense4, dim3(ntiles_of(g)), dim3(256), 0, s, (float2*)psi, (const float4*)mats, g.W, pd);
     return hipGetLastError();
 }
