@@ -1138,11 +1138,17 @@ __global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T)
             const int u0 = pass_u0(pd, g);
             const int nops = pass_nops(pd, g);
             const uint32_t b0 = fl_spread(active ? threadIdx.x : 0u, u0, R);
+            // byte offset of element b0 | m << u0: slot(b0) ^ slot(m << u0), the
+            // second part uniform (the swizzle is linear over XOR)
+            const uint32_t vb = fl_swz(b0) * (uint32_t)sizeof(cplx);
+            auto loff = [&](int m) { return vb ^ (fl_swz((uint32_t)m << u0) * (uint32_t)sizeof(cplx)); };
+            char* const pb = reinterpret_cast<char*>(lp);
+            char* const lb = reinterpret_cast<char*>(ll);
             T pr[1 << R], pi[1 << R], lr[1 << R], li[1 << R];
 #pragma unroll
             for (int m = 0; m < (1 << R); ++m) {
-                const uint32_t idx = fl_swz(b0 | ((uint32_t)m << u0));
-                cplx a = lp[idx], b = ll[idx];
+                const uint32_t o = loff(m);
+                cplx a = *reinterpret_cast<const cplx*>(pb + o), b = *reinterpret_cast<const cplx*>(lb + o);
                 if (!active) { a.x = a.y = b.x = b.y = 0; }
                 pr[m] = a.x;
                 pi[m] = a.y;
@@ -1189,14 +1195,14 @@ __global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T)
             if (active) {
 #pragma unroll
                 for (int m = 0; m < (1 << R); ++m) {
-                    const uint32_t idx = fl_swz(b0 | ((uint32_t)m << u0));
+                    const uint32_t o = loff(m);
                     cplx a, b;
                     a.x = pr[m];
                     a.y = pi[m];
                     b.x = lr[m];
                     b.y = li[m];
-                    lp[idx] = a;
-                    ll[idx] = b;
+                    *reinterpret_cast<cplx*>(pb + o) = a;
+                    *reinterpret_cast<cplx*>(lb + o) = b;
                 }
             }
             __syncthreads();
