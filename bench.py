@@ -74,10 +74,11 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo", "gue"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue", "long"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
-                         "or heating of the paper's GUE circuit versus drive frequency (gue)")
+                         "heating of the paper's GUE circuit versus drive frequency (gue), or the energy "
+                         "density every 100 periods of a long run (long, with --L 34)")
     ap.add_argument("--max-periods", type=int, default=10000)
     ap.add_argument("--variants", type=str, default="plain,dense6_fp32,dense6_bf16x3",
                     help="complex64 variants of --study precision")
@@ -319,6 +320,34 @@ def gue_study(fl, torch, L, omegas, tmax, nrec=240):
             "sigma_inf": float(np.sqrt(var)), "fit": fit, "rows": out}
 
 
+def long_run(fl, torch, L, nmax, every=100):
+    """The long run of the paper's largest single-device size (Sec. IV): the
+    XYZ+fields chain at L (complex64, in place), the energy density every
+    `every` periods up to nmax periods; periods/s of the whole run."""
+    import floquet_inputs as fin
+    w = fin.xyz_workload(L)
+    eng = fl.FloquetEngine(L, "c64")
+    eng.set_xyz(w["J"], w["fields"], w["T"])
+    psi = eng.new_state()
+    eng.init(psi, w["spinors"])
+    E, N = eng.energy(psi)
+    rows = [{"period": 0, "e": E / (L * N), "norm_minus_1": N - 1.0}]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n = 0
+    while n < nmax:
+        k = min(every, nmax - n)
+        eng.step(psi, k)
+        n += k
+        E, N = eng.energy(psi)
+        rows.append({"period": n, "e": E / (L * N), "norm_minus_1": N - 1.0,
+                     "elapsed_s": round(time.perf_counter() - t0, 2)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    wall = time.perf_counter() - t0
+    return {"study": "long", "L": L, "periods": n, "every": every, "wall_s": round(wall, 2),
+            "periods_per_s": round(n / wall, 3), "rows": rows}
+
+
 def l34_leg(fl, torch, periods=16):
     """L = 34 complex64 (128 GiB) in place: periods/s of the plain sweep and
     the energy density after the run."""
@@ -370,6 +399,9 @@ def main():
         return
     if args.study == "echo":
         print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
+        return
+    if args.study == "long":
+        print(json.dumps(long_run(fl, torch, L, args.max_periods)), flush=True)
         return
     if args.study == "gue":
         omegas = [float(x) for x in args.omegas.split(",")]
