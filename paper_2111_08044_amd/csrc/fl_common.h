@@ -97,8 +97,9 @@ FL_HD uint64_t fl_tile_offset(uint32_t j, int C, int h) {
 }
 
 // LDS slot of tile-local amplitude j.  XOR-ing bits 4..7 into bits 0..3
-// makes every register-group access pattern hit 16 distinct 8-byte slots
-// within each run of 16 lanes, whatever u0 is.
+// makes the access patterns of 4-bit register groups (any first bit u0) and
+// of pairwise tile loads hit 16 distinct 8-byte slots within each run of 16
+// lanes.  The function is linear over XOR: slot(a ^ b) = slot(a) ^ slot(b).
 FL_HD uint32_t fl_swz(uint32_t j) { return j ^ ((j >> 4) & 15u); }
 
 // Insert R zero bits at position u0 into o.

@@ -355,6 +355,24 @@ __device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
 // contiguous amplitudes (>= 128 bytes), so every access coalesces.  This
 // saves one LDS round trip and one barrier at each end of the pass.  Groups
 // starting lower go through the LDS transpose, as every middle group does.
+//
+// LDS slots of the complex64 sweep (13 tile bits, 5 register bits).  Each run
+// of 16 lanes of an 8-byte LDS access must hit 16 distinct slots modulo 16.
+// In a register group with first bit u0 the 16 lanes vary the four lowest
+// tile bits outside [u0, u0 + 5): bits 5..8 for u0 = 0, {0, 6, 7, 8} for
+// u0 = 1, and so on.  fl_swz (bits 4..7 into bits 0..3) misses bit 8 and gives
+// two-way conflicts for u0 < 4; XOR-ing bits 5..8 into bits 0..3 and bit 4
+// into bit 0 keeps every one of these patterns and the pairwise tile
+// loads (lanes varying bits 1..4) conflict-free.  Like fl_swz it is linear
+// over XOR, its added term depends on none of bits 0..3, and it leaves every
+// bit from 9 up alone.
+// The complex128 sweep (12 tile bits, 4 register bits) keeps fl_swz.
+template <typename T>
+__device__ __forceinline__ uint32_t sweep_swz(uint32_t j) {
+    if constexpr (sizeof(T) == 4) return j ^ ((j >> 5) & 15u) ^ ((j >> 4) & 1u);
+    else return fl_swz(j);
+}
+
 template <typename T, int R, int KT, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_sweep_tiles(typename CT<T>::c* __restrict__ psi,
                                                     const T* __restrict__ gates, int W, fl_pass pd) {
@@ -375,9 +393,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     static_assert((APL * NT) % (1 << C) == 0 && (APL * NT) % 256 == 0, "tile access stride");
     const uint64_t toff = fl_tile_offset(APL * threadIdx.x, C, h);
     const uint64_t tstride = (uint64_t)((APL * NT) >> C) << h;
-    // LDS slot of element j + s APL NT is fl_swz(j) + s APL NT (the swizzle
-    // only mixes bits 0..7), and fl_swz(j + 1) = fl_swz(j) ^ 1 for even j.
-    const uint32_t l0 = fl_swz(APL * threadIdx.x);
+    // LDS slot of element j + s APL NT is sweep_swz(j) + s APL NT (the
+    // swizzle only mixes bits 0..8), and sweep_swz(j + 1) = sweep_swz(j) ^ 1
+    // for even j.
+    const uint32_t l0 = sweep_swz<T>(APL * threadIdx.x);
     const bool din = ng > 0 && pass_u0(pd, 0) >= FL_DIRECT_MIN_U0;
     const bool dout = ng > 0 && pass_u0(pd, ng - 1) >= FL_DIRECT_MIN_U0;
 
@@ -413,11 +432,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     auto lds_addrs = [&](int u0) {
         uint32_t bk[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) bk[k] = fl_swz(1u << (u0 + k)) * (uint32_t)sizeof(cplx);
+        for (int k = 0; k < R; ++k) bk[k] = sweep_swz<T>(1u << (u0 + k)) * (uint32_t)sizeof(cplx);
 #pragma unroll
         for (int s = 0; s < SUB; ++s) {
             b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
-            la[s][0] = fl_swz(b0[s]) * (uint32_t)sizeof(cplx);
+            la[s][0] = sweep_swz<T>(b0[s]) * (uint32_t)sizeof(cplx);
 #pragma unroll
             for (int m = 1; m < (1 << R); ++m) la[s][m] = la[s][m & (m - 1)] ^ bk[__builtin_ctz(m)];
         }

@@ -126,6 +126,68 @@ std::vector<Gate> pack_groups(const fl_geom& g, std::vector<Gate> rem, fl_pass& 
     return rem;
 }
 
+// The kernels apply a group's ops two at a time; an odd count costs a copy of
+// the register group after the last op.  Shift ops across the boundary of
+// consecutive groups, which keeps the pass's op sequence unchanged, wherever
+// the op's bits lie inside the other group's register bits, so that fewer
+// groups have odd counts; groups left empty are dropped (one LDS exchange
+// less).
+void balance_groups(const fl_geom& g, fl_pass& pd) {
+    auto fits = [&](int gi, int u) { return u >= pd.u0[gi] && u + 1 < pd.u0[gi] + g.R; };
+    auto set_op = [&](int gi, int k, int u, int16_t gate, int16_t slot) {
+        pd.opi[gi][k] = (int8_t)(u - pd.u0[gi]);
+        pd.opg[gi][k] = gate;
+        pd.ops[gi][k] = slot;
+    };
+    for (int gi = 0; gi + 1 < pd.ngroups; ++gi) {
+        if (!(pd.nops[gi] & 1)) continue;
+        const int a = gi, b = gi + 1;
+        const int kl = pd.nops[a] - 1;
+        const int ul = pd.u0[a] + pd.opi[a][kl];
+        if (fits(b, ul) && pd.nops[b] < FL_MAX_OPS) {
+            // the last op of a becomes the first op of b
+            for (int k = pd.nops[b]; k > 0; --k) {
+                pd.opi[b][k] = pd.opi[b][k - 1];
+                pd.opg[b][k] = pd.opg[b][k - 1];
+                pd.ops[b][k] = pd.ops[b][k - 1];
+            }
+            set_op(b, 0, ul, pd.opg[a][kl], pd.ops[a][kl]);
+            pd.nops[b]++;
+            pd.nops[a]--;
+            continue;
+        }
+        if (pd.nops[b] == 0) continue;
+        const int uf = pd.u0[b] + pd.opi[b][0];
+        if (fits(a, uf) && pd.nops[a] < FL_MAX_OPS) {
+            // the first op of b becomes the last op of a
+            set_op(a, pd.nops[a], uf, pd.opg[b][0], pd.ops[b][0]);
+            pd.nops[a]++;
+            for (int k = 0; k + 1 < pd.nops[b]; ++k) {
+                pd.opi[b][k] = pd.opi[b][k + 1];
+                pd.opg[b][k] = pd.opg[b][k + 1];
+                pd.ops[b][k] = pd.ops[b][k + 1];
+            }
+            pd.nops[b]--;
+        }
+    }
+    int out = 0;
+    for (int gi = 0; gi < pd.ngroups; ++gi) {
+        if (pd.nops[gi] == 0) continue;
+        if (out != gi) {
+            pd.u0[out] = pd.u0[gi];
+            pd.nops[out] = pd.nops[gi];
+            for (int k = 0; k < pd.nops[gi]; ++k) {
+                pd.opi[out][k] = pd.opi[gi][k];
+                pd.opg[out][k] = pd.opg[gi][k];
+                pd.ops[out][k] = pd.ops[gi][k];
+            }
+        }
+        ++out;
+    }
+    for (int gi = out; gi < pd.ngroups; ++gi) pd.nops[gi] = 0;
+    pd.ngroups = out;
+}
+
 // Passes the plain greedy rule (the window admitting the most gates) needs to
 // finish the circuit from state s.
 int greedy_passes(const fl_geom& g, const std::vector<int>& windows, Sched s, int cap) {
@@ -205,6 +267,9 @@ std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_
         std::memset(&pd, 0, sizeof(pd));
         pd.h = best_h;
         std::vector<Gate> left = pack_groups(g, gl, pd);
+#if !defined(FL_NO_BALANCE)
+        balance_groups(g, pd);
+#endif
         if (with_slots) {
             // map the bonds of this pass to local reduction slots
             int map[64];
