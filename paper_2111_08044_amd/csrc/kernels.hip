@@ -1457,19 +1457,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
     tile_load<float, K>(psi, base, K, C, h, lds);
     __syncthreads();
-    for (int g = 0; g < pd.ngroups; ++g) {
-        const int u0 = pass_u0(pd, g);
-        // 64 lanes x 16 floats (4 KiB) per window
+    // A fragments of a window: 64 lanes x 16 floats (4 KiB).  The next
+    // window's fragments are fetched while the current window is applied; the
+    // last window fetches its own again, so that no branch lets the loads
+    // drift down to their use.
+    auto load_a = [&](int g, float (&dst)[16]) {
         const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 256 + (size_t)lane * 4;
-        float a[16];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const float4 t = M[q];
-            a[4 * q] = t.x;
-            a[4 * q + 1] = t.y;
-            a[4 * q + 2] = t.z;
-            a[4 * q + 3] = t.w;
+            dst[4 * q] = t.x;
+            dst[4 * q + 1] = t.y;
+            dst[4 * q + 2] = t.z;
+            dst[4 * q + 3] = t.w;
         }
+    };
+    float a[16], an[16];
+    if (pd.ngroups > 0) load_a(0, a);
+    for (int g = 0; g < pd.ngroups; ++g) {
+        const int u0 = pass_u0(pd, g);
+        load_a(g + 1 < pd.ngroups ? g + 1 : g, an);
+        __builtin_amdgcn_sched_barrier(0);
         // slot(spread(col) | s << u0) = slot(spread(col)) ^ slot(s << u0): the
         // second part is uniform (the swizzle is linear over XOR)
         uint32_t vb[4];
@@ -1507,6 +1515,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + (vb[cb] ^ (fl_swz(m << u0) * 8u))) = v;
                 }
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k) a[k] = an[k];
     }
     tile_store<float, K>(psi, base, K, C, h, lds);
 }
