@@ -39,7 +39,7 @@ PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # WRITE_SIZE read 8.0 GiB -> x1).  Valid only for the kernel code it was taken
 # on: the key is a hash of kernels.hip and fl_common.h with comments and
 # whitespace removed.
-TRAFFIC = {"kernel_code_sha256_16": "109e296194e6ebd1", "fetch_gib_raw": 4.0002, "fetch_scale": 2.0,
+TRAFFIC = {"kernel_code_sha256_16": "404242653bf23282", "fetch_gib_raw": 4.0002, "fetch_scale": 2.0,
            "write_gib_raw": 8.0, "write_scale": 1.0}
 
 
@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--omegas", type=str, default="5,5.5,6,6.5,7,7.5,8",
                     help="drive frequencies of --study gue")
     ap.add_argument("--tmax", type=float, default=2e5, help="longest time (units of 1/J) of --study gue")
+    ap.add_argument("--sweep-only", type=int, default=0, metavar="N",
+                    help="only initialise the state and run N periods of the plain sweep, then exit "
+                         "(a short program for hardware counter runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the state once (a plain device copy of known size, the reference "
                          "for scaling hardware byte counters)")
@@ -412,6 +415,12 @@ def main():
     eng.set_xyz(w["J"], w["fields"], w["T"])
     psi = eng.new_state()
     eng.init(psi, w["spinors"])
+    if args.sweep_only > 0:
+        eng.step(psi, args.sweep_only)
+        torch.cuda.synchronize()
+        print(json.dumps({"sweep_only": args.sweep_only, "L": L, "sweep_launches": plan_passes(fl, L, args.sweep_only)}),
+              flush=True)
+        return
     if args.calibrate_copy:
         tmp = torch.empty_like(psi)
         tmp.copy_(psi)

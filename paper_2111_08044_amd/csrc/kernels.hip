@@ -345,6 +345,51 @@ __device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
 // lgkmcnt(0) with no wait on the vector-memory and export counters.
 #define FL_WAIT_LGKM0 0xc07f
 
+// The ops of register group g applied to the SUB register groups of a
+// thread.  Ops run two per iteration (the register copies that LLVM places on
+// a loop back edge after the 4-way choice of gate bits are then not needed at
+// all).  The next op's gate (32 scalar registers) is fetched while the
+// current one is applied; an explicit lgkmcnt(0) before each fetch waits for
+// the previous one, so that no wait inside an apply ever covers the fetch in
+// flight.
+template <typename T, int R, int SUB>
+__device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SUB][1 << R], const fl_pass& pd, int g,
+                                                const T* __restrict__ gates) {
+    const int nops = pass_nops(pd, g);
+    T gc[32];
+    {
+        const T* G = gates + 32 * pass_gate(pd, g, 0);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) gc[k] = G[k];
+    }
+    int i = pass_bit(pd, g, 0);
+    for (int q = 0; q < nops; q += 2) {
+        __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+        const int q1 = (q + 1 < nops) ? q + 1 : q;
+        const int i1 = pass_bit(pd, g, q1);
+        T g1[32];
+        {
+            const T* G = gates + 32 * pass_gate(pd, g, q1);
+#pragma unroll
+            for (int k = 0; k < 32; ++k) g1[k] = G[k];
+        }
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
+        if (q + 1 < nops) {
+            __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+            const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
+            i = pass_bit(pd, g, q2);
+            {
+                const T* G = gates + 32 * pass_gate(pd, g, q2);
+#pragma unroll
+                for (int k = 0; k < 32; ++k) gc[k] = G[k];
+            }
+#pragma unroll
+            for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i1, g1);
+        }
+    }
+}
+
 // Full-size tiles (K = KT), one tile per workgroup.  Every thread holds SUB
 // register groups of 2^R amplitudes and applies each gate to all of them; the
 // next gate's matrix is fetched while the current one is applied.
@@ -498,47 +543,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
 
     for (int g = 0; g < ng; ++g) {
         const int u0 = pass_u0(pd, g);
-        const int nops = pass_nops(pd, g);
         if (g > 0 || din) lds_addrs(u0);
         if (g > 0) lds_to_regs();
-        // Ops run two per iteration (the register copies that LLVM places on
-        // a loop back edge after the 4-way choice of gate bits are then not
-        // needed at all).  The next op's gate (32 scalar registers) is fetched
-        // while the current one is applied; an explicit lgkmcnt(0) before each
-        // fetch waits for the previous one, so that no wait inside an apply
-        // ever covers the fetch in flight.
-        T gc[32];
-        {
-            const T* G = gates + 32 * pass_gate(pd, g, 0);
-#pragma unroll
-            for (int k = 0; k < 32; ++k) gc[k] = G[k];
-        }
-        int i = pass_bit(pd, g, 0);
-        for (int q = 0; q < nops; q += 2) {
-            __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
-            const int q1 = (q + 1 < nops) ? q + 1 : q;
-            const int i1 = pass_bit(pd, g, q1);
-            T g1[32];
-            {
-                const T* G = gates + 32 * pass_gate(pd, g, q1);
-#pragma unroll
-                for (int k = 0; k < 32; ++k) g1[k] = G[k];
-            }
-#pragma unroll
-            for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
-            if (q + 1 < nops) {
-                __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
-                const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
-                i = pass_bit(pd, g, q2);
-                {
-                    const T* G = gates + 32 * pass_gate(pd, g, q2);
-#pragma unroll
-                    for (int k = 0; k < 32; ++k) gc[k] = G[k];
-                }
-#pragma unroll
-                for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i1, g1);
-            }
-        }
+        sweep_group_ops<T, R, SUB>(vr, vi, pd, g, gates);
         if (g == ng - 1 && dout) break;
         regs_to_lds();
         __syncthreads();
