@@ -46,9 +46,6 @@
 #ifndef FL_DIRECT_MIN_U0
 #define FL_DIRECT_MIN_U0 4   // lowest group bit for direct HBM <-> register transfers
 #endif
-#ifndef FL_SWEEP_GATE_PREFETCH
-#define FL_SWEEP_GATE_PREFETCH 1  // 1: fetch the next gate matrix during the current one
-#endif
 
 struct fl_pass {
     int32_t h;                               // first physical bit of the high window
