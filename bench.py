@@ -74,11 +74,12 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo", "gue", "long"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue", "long", "oracle-scaling"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
                          "heating of the paper's GUE circuit versus drive frequency (gue), or the energy "
-                         "density every 100 periods of a long run (long, with --L 34)")
+                         "density every 100 periods of a long run (long, with --L 34), or the CPU "
+                         "oracle's time per period at L = 20..28 (oracle-scaling, no GPU)")
     ap.add_argument("--max-periods", type=int, default=10000)
     ap.add_argument("--variants", type=str, default="plain,dense6_fp32,dense6_bf16x3",
                     help="complex64 variants of --study precision")
@@ -146,6 +147,36 @@ def cpu_baseline(L, nsample):
                       f"{dt:.1f} s, scaled by {L - 1} gates/period; numpy einsum, single thread",
             "s_per_period": s_per_period, "host": platform.processor() or platform.machine(),
             "host_cpus": os.cpu_count()}
+
+
+def oracle_scaling(Ls, nrep=2):
+    """Wall time of one full period of the oracle (FP64, one gate at a time)
+    at several chain lengths, fitted to a L 2^L (the cost the paper states,
+    Sec. V), and the fit's value at L = 30 beside the direct L = 30 sample of
+    cpu_baseline."""
+    import numpy as np
+
+    import floquet_inputs as fin
+    import oracle as O
+    rows = []
+    for L in Ls:
+        w = fin.xyz_workload(L)
+        hs = O.xyz_bond_hamiltonians(L, w["J"], w["fields"])
+        G = O.floquet_gates(hs, w["T"])
+        psi0 = O.product_state(w["spinors"])
+        best = float("inf")
+        for _ in range(nrep if L < 28 else 1):
+            t0 = time.perf_counter()
+            O.evolve(psi0, L, G, 1)
+            best = min(best, time.perf_counter() - t0)
+        rows.append({"L": L, "s_per_period": round(best, 4), "ns_per_amp_gate": round(1e9 * best / ((L - 1) * 2.0**L), 3)})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    x = np.array([r["L"] * 2.0**r["L"] for r in rows])
+    t = np.array([r["s_per_period"] for r in rows])
+    a = float(np.dot(t, x) / np.dot(x, x))
+    return {"study": "oracle-scaling", "fit": "t = a L 2^L", "a_ns": round(a * 1e9, 4),
+            "fit_s_per_period_L30": round(a * 30 * 2.0**30, 2), "rows": rows, "cores": 1,
+            "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
 
 def adjoint_ratio(fl, torch, L=24, n=200, K=50):
@@ -389,6 +420,9 @@ def main():
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
+    if args.study == "oracle-scaling":
+        print(json.dumps(oracle_scaling([20, 22, 24, 26, 28])), flush=True)
+        return
     import numpy as np
     import torch
 
