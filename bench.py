@@ -74,12 +74,14 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo", "gue", "long", "oracle-scaling"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue", "long"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
                          "heating of the paper's GUE circuit versus drive frequency (gue), or the energy "
-                         "density every 100 periods of a long run (long, with --L 34), or the CPU "
-                         "oracle's time per period at L = 20..28 (oracle-scaling, no GPU)")
+                         "density every 100 periods of a long run (long, with --L 34)")
+    ap.add_argument("--cpu-baseline-scaling", action="store_true",
+                    help="only the cpu_baseline leg, at L = 20..28: the oracle's time per period and its "
+                         "a L 2^L fit (no GPU)")
     ap.add_argument("--max-periods", type=int, default=10000)
     ap.add_argument("--variants", type=str, default="plain,dense6_fp32,dense6_bf16x3",
                     help="complex64 variants of --study precision")
@@ -149,11 +151,11 @@ def cpu_baseline(L, nsample):
             "host_cpus": os.cpu_count()}
 
 
-def oracle_scaling(Ls, nrep=2):
-    """Wall time of one full period of the oracle (FP64, one gate at a time)
-    at several chain lengths, fitted to a L 2^L (the cost the paper states,
-    Sec. V), and the fit's value at L = 30 beside the direct L = 30 sample of
-    cpu_baseline."""
+def cpu_baseline_scaling(Ls, nrep=2):
+    """The cpu_baseline leg at several chain lengths: wall time of one full
+    period of the oracle (FP64, one gate at a time), fitted to a L 2^L (the
+    cost the paper states, Sec. V), and the fit's value at L = 30 beside the
+    direct L = 30 sample of cpu_baseline."""
     import numpy as np
 
     import floquet_inputs as fin
@@ -174,7 +176,7 @@ def oracle_scaling(Ls, nrep=2):
     x = np.array([r["L"] * 2.0**r["L"] for r in rows])
     t = np.array([r["s_per_period"] for r in rows])
     a = float(np.dot(t, x) / np.dot(x, x))
-    return {"study": "oracle-scaling", "fit": "t = a L 2^L", "a_ns": round(a * 1e9, 4),
+    return {"cpu_baseline_scaling": "oracle", "fit": "t = a L 2^L", "a_ns": round(a * 1e9, 4),
             "fit_s_per_period_L30": round(a * 30 * 2.0**30, 2), "rows": rows, "cores": 1,
             "host": platform.processor() or platform.machine(), "host_cpus": os.cpu_count()}
 
@@ -420,8 +422,8 @@ def main():
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-    if args.study == "oracle-scaling":
-        print(json.dumps(oracle_scaling([20, 22, 24, 26, 28])), flush=True)
+    if args.cpu_baseline_scaling:
+        print(json.dumps(cpu_baseline_scaling([20, 22, 24, 26, 28])), flush=True)
         return
     import numpy as np
     import torch
