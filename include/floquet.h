@@ -198,9 +198,11 @@ int fl_tile_map(int L, int dtype, int h, uint64_t *out);
 int fl_host_window_matrix(const double *G, const int *pos, int nops, int mode, double *U_out, void *frag_out);
 
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
- * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover,
- * 3 = cover used for H0 psi, 4 = dense 6-qubit-window sweep, 5 = dense
- * 4-qubit-window sweep), flattened as int32:
+ * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover on
+ * 12-bit tiles (complex128, and complex64 with L <= 13), 3 = cover used for
+ * H0 psi, 4 = dense 6-qubit-window sweep, 5 = dense 4-qubit-window sweep,
+ * 6 = energy / density-matrix cover of complex64 states with L >= 14: 13-bit
+ * tiles, bonds packed into 5-bit register groups), flattened as int32:
  * [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {i, gate, slot}*}*}*].
  * Writes at most cap words to buf (may be NULL) and the required count to
  * *needed. */

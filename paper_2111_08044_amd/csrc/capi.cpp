@@ -76,6 +76,9 @@ struct fl_ctx {
     std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
     std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
     std::vector<fl_win> cover_win;    // per cover_rdm pass: window-bond form (h < 0: not eligible)
+    bool use_grp = false;             // complex64, L >= 14: the reductions run on 13-bit tiles
+    fl_geom geom_grp{};               // (L, 13, 5)
+    std::vector<fl_pass> cover_grp;   // bond cover of geom_grp in register groups
 };
 
 namespace {
@@ -177,6 +180,15 @@ void rho_from16(const double* v, cd* rho) {
 }
 
 int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
+    if (c->use_grp) {
+        const int grid = (int)std::min<uint32_t>(ntiles(c->geom_grp), kReduceGrid);
+        for (const fl_pass& p : c->cover_grp) {
+            hipError_t e = fl::launch_rdm_groups(c->geom_grp, psi, p, c->d_part, grid, c->L, c->stream);
+            if (e != hipSuccess) return fail_hip(e, "k_rdm_groups launch");
+        }
+        *grid_out = grid;
+        return FL_OK;
+    }
     const int grid = (int)std::min<uint32_t>(ntiles(c->geom_rdm), kReduceGrid);
     for (size_t k = 0; k < c->cover_rdm.size(); ++k) {
         const fl_win& w = c->cover_win[k];
@@ -369,6 +381,11 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
     c->cover_rdm = fl::plan_cover(c->geom_rdm);
+    c->use_grp = FL_RDM_GROUPS && dtype == FL_C64 && L > FL_KMAX_C64;
+    if (c->use_grp) {
+        c->geom_grp = fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64);
+        c->cover_grp = fl::plan_cover_groups(c->geom_grp);
+    }
     // complex64 passes whose bonds all lie inside the high window (no low-bit
     // bond, no norm) run in the register-window reduction kernel
     for (const fl_pass& p : c->cover_rdm) {
@@ -876,8 +893,12 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     } else if (kind == 3) {
         g = fl::make_geom(L, kmax_of(dtype), 4);
         plan = fl::plan_cover(g);
+    } else if (kind == 6) {
+        if (dtype != FL_C64 || L <= FL_KMAX_C64) return fail(FL_EINVAL, "the grouped cover needs complex64 and L >= 14");
+        g = fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64);
+        plan = fl::plan_cover_groups(g);
     } else {
-        return fail(FL_EINVAL, "kind must be 0..5");
+        return fail(FL_EINVAL, "kind must be 0..6");
     }
     std::vector<int> words;
     fl::serialize_plan(g, plan, words);

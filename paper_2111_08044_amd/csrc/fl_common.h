@@ -43,6 +43,9 @@
 #ifndef FL_SWEEP_R_C64
 #define FL_SWEEP_R_C64 5     // register bits per group of the complex64 sweep
 #endif
+#ifndef FL_RDM_GROUPS
+#define FL_RDM_GROUPS 1      // complex64 reductions on 13-bit tiles with register groups (L >= 14)
+#endif
 #ifndef FL_DIRECT_MIN_U0
 #define FL_DIRECT_MIN_U0 4   // lowest group bit for direct HBM <-> register transfers
 #endif

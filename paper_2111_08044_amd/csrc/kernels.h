@@ -10,6 +10,10 @@ namespace fl {
 hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gates, const fl_pass& pd, hipStream_t s);
 hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
                       int nslot, hipStream_t s);
+// complex64 bond reductions over full 13-bit tiles; pd from plan_cover_groups
+// of geometry (L, 13, 5) (L >= 14)
+hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
+                             int nslot, hipStream_t s);
 // complex64 window-bond pass (see k_rdm_win); the geometry must have W = FL_KMAX_RDM - FL_LOWBITS
 hipError_t launch_rdm_win(const fl_geom& g, const void* psi, const fl_win& pw, double* partials, int grid, int nslot,
                           hipStream_t s);

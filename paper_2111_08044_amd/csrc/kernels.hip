@@ -873,6 +873,149 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
     }
 }
 
+// Bond reductions of complex64 states over full 13-bit tiles with 5-bit
+// register groups (the layout of the complex64 sweep): a cover pass's bonds
+// come packed into groups of R consecutive tile bits, every thread reads a
+// group's 2^R amplitudes from LDS once and forms the sums of all the group's
+// bonds from registers (8 quads per bond and thread), so each LDS word is read
+// once per group rather than once per bond.  Per tile, each lane sums its
+// quads in FP32, the wave sums the lanes in FP32 (512 quads), and the result
+// goes into FP64 per-wave LDS accumulators; the norm is summed in FP32 per
+// tile and in FP64 across tiles.  Persistent workgroups; partials as in
+// k_rdm_tiles.
+template <int A, int B, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (A < B) {
+        f(std::integral_constant<int, A>{});
+        static_for<A + 1, B>(f);
+    }
+}
+
+template <int R, int I>
+__device__ __forceinline__ void group_bond_sums(const float (&vr)[1 << R], const float (&vi)[1 << R], float (&r)[16]) {
+    // (immediate-operand markers keep the bit variants apart, as in apply_pair_g)
+    __asm__ volatile("; bond sums on register bits %0" ::"i"(I));
+#pragma unroll
+    for (int c = 0; c < (1 << R) / 4; ++c) {
+        const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
+        float ar[4], ai[4];
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            ar[l] = vr[b | (l << I)];
+            ai[l] = vi[b | (l << I)];
+        }
+        rdm_quad<float>(ar, ai, r);
+    }
+    __asm__ volatile("; end bond sums on register bits %0" ::"i"(I));
+}
+
+template <int R, int KT, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_rdm_groups(
+    const float2* __restrict__ psi, int W, uint32_t ntiles, fl_pass pd, double* __restrict__ partials, int nslot) {
+    constexpr int C = FL_LOWBITS;
+    constexpr int K = KT;
+    static_assert((1 << (K - R)) == NT, "one register group per thread");
+    constexpr int ITER = (1 << K) / (2 * NT);
+    constexpr int NW = NT / 64;
+    constexpr int NS = FL_RDM_TILE_MAXG;   // bond rows (K - 1 at most) + the norm
+    static_assert(K - 1 < NS, "bond rows");
+    __shared__ __attribute__((aligned(16))) float2 lds[1 << K];
+    __shared__ double wacc[NW][NS][16];
+    const char* const lb = reinterpret_cast<const char*>(lds);
+    const int h = pd.h;
+    const int ng = pd.ngroups;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int t = threadIdx.x; t < NW * NS * 16; t += NT) (&wacc[0][0][0])[t] = 0.0;
+    double nrm = 0.0;
+    static_assert((2 * NT) % (1 << C) == 0, "tile access stride");
+    // element 2 (tid + s NT) of a tile sits at toff + s tstride, LDS slot
+    // sweep_swz(j) + s 2 NT, and sweep_swz(j + 1) = sweep_swz(j) ^ 1
+    const uint64_t toff = fl_tile_offset(2 * threadIdx.x, C, h);
+    const uint64_t tstride = (uint64_t)((2 * NT) >> C) << h;
+    const uint32_t l0 = sweep_swz<float>(2 * threadIdx.x);
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const float2* src = psi + fl_tile_base(tile, C, W, h) + toff;
+        float4 v[ITER];
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) v[s] = *reinterpret_cast<const float4*>(src + s * tstride);
+        __syncthreads();   // the previous tile's LDS reads (and the accumulator reset) are done
+        float tn = 0.f;
+#pragma unroll
+        for (int s = 0; s < ITER; ++s) {
+            const uint32_t l = l0 + s * (2 * NT);
+            lds[l] = make_float2(v[s].x, v[s].y);
+            lds[l ^ 1] = make_float2(v[s].z, v[s].w);
+            tn = fmaf(v[s].x, v[s].x, fmaf(v[s].y, v[s].y, fmaf(v[s].z, v[s].z, fmaf(v[s].w, v[s].w, tn))));
+        }
+        nrm += (double)tn;
+        __syncthreads();
+        int row = 0;
+        for (int g = 0; g < ng; ++g) {
+            const int u0 = pass_u0(pd, g);
+            const int nops = pass_nops(pd, g);
+            // slot(b0 | m << u0) = slot(b0) ^ XOR of the slots of m's set bits
+            uint32_t bk[R];
+#pragma unroll
+            for (int k = 0; k < R; ++k) bk[k] = sweep_swz<float>(1u << (u0 + k)) * 8u;
+            uint32_t la[1 << R];
+            la[0] = sweep_swz<float>(fl_spread(threadIdx.x, u0, R)) * 8u;
+#pragma unroll
+            for (int m = 1; m < (1 << R); ++m) la[m] = la[m & (m - 1)] ^ bk[__builtin_ctz(m)];
+            float vr[1 << R], vi[1 << R];
+#pragma unroll
+            for (int m = 0; m < (1 << R); ++m) {
+                const float2 a = *reinterpret_cast<const float2*>(lb + la[m]);
+                vr[m] = a.x;
+                vi[m] = a.y;
+            }
+            // the group's bonds sit on pair bits i (ops in increasing i): one
+            // compile-time code block per pair position, run when present
+            uint32_t present = 0;
+            for (int k = 0; k < nops; ++k) present |= 1u << pass_bit(pd, g, k);
+            static_for<0, R - 1>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if ((present >> i) & 1u) {
+                    float r[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) r[q] = 0.f;
+                    group_bond_sums<R, i>(vr, vi, r);
+                    // lane l holds the sum of value l >> 2; one lane of each four
+                    // adds it, the others add zero (an LDS atomic with every lane active)
+                    const float red = wave_transpose_reduce<float, 16>(r);
+                    const int rw = row + __builtin_popcount(present & ((1u << i) - 1u));
+                    __hip_atomic_fetch_add(&wacc[wave][rw][lane >> 2], (lane & 3) == 0 ? (double)red : 0.0,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            });
+            row += nops;
+        }
+    }
+    double nv[1] = {nrm};
+    const double ntot = wave_transpose_reduce<double, 1>(nv);
+    __syncthreads();
+    if (lane == 0) wacc[wave][NS - 1][0] = ntot;
+    __syncthreads();
+    // rows of the pass in group order -> partials[block][bond][16]
+    int nrows = 0;
+    for (int g = 0; g < ng; ++g) nrows += pass_nops(pd, g);
+    for (int t = threadIdx.x; t < (nrows + 1) * 16; t += NT) {
+        const int row = t >> 4, v = t & 15;
+        if (row == nrows && v > 0) continue;
+        const int rr = row < nrows ? row : NS - 1;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) sum += wacc[w][rr][v];
+        if (row < nrows) {
+            // the bond of row `row`: walk the groups
+            int gg = 0, k = row;
+            while (k >= pass_nops(pd, gg)) k -= pass_nops(pd, gg++);
+            partials[((size_t)blockIdx.x * nslot + pd.ops[gg][k]) * 16 + v] = sum;
+        } else if (pd.flags & 1) {
+            partials[((size_t)blockIdx.x * nslot + (nslot - 1)) * 16] = sum;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // product state, overlap, finalize
 // ---------------------------------------------------------------------------
@@ -1586,6 +1729,14 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
             hipLaunchKernelGGL((k_rdm<double, 0, FL_KMAX_RDM>), dim3(grid), dim3(FL_NT), 0, s, p, g.C, g.W, nt, pd,
                                partials, nslot);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
+                             int nslot, hipStream_t s) {
+    if (g.K != FL_KMAX_C64 || g.R != FL_SWEEP_R_C64 || g.W == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rdm_groups<FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(grid), dim3(FL_SWEEP_NT_C64), 0,
+                       s, (const float2*)psi, g.W, ntiles_of(g), pd, partials, nslot);
     return hipGetLastError();
 }
 

@@ -343,6 +343,37 @@ std::vector<fl_pass> plan_cover(const fl_geom& g) {
     return plan;
 }
 
+std::vector<fl_pass> plan_cover_groups(const fl_geom& g) {
+    std::vector<fl_pass> plan = plan_cover(g);
+    for (fl_pass& pd : plan) {
+        // (tile bit, bond) of every bond of the pass, by tile bit
+        std::vector<std::pair<int, int>> bonds;
+        for (int gi = 0; gi < pd.ngroups; ++gi) bonds.emplace_back((int)pd.u0[gi], (int)pd.ops[gi][0]);
+        std::sort(bonds.begin(), bonds.end());
+        fl_pass q;
+        std::memset(&q, 0, sizeof(q));
+        q.h = pd.h;
+        q.flags = pd.flags;
+        size_t k = 0;
+        while (k < bonds.size()) {
+            const int u0 = std::min(bonds[k].first, g.K - g.R);
+            const int gi = q.ngroups++;
+            q.u0[gi] = (int8_t)u0;
+            int n = 0;
+            while (k < bonds.size() && bonds[k].first + 1 < u0 + g.R) {
+                q.opi[gi][n] = (int8_t)(bonds[k].first - u0);
+                q.opg[gi][n] = -1;
+                q.ops[gi][n] = (int16_t)bonds[k].second;
+                ++n;
+                ++k;
+            }
+            q.nops[gi] = (int8_t)n;
+        }
+        pd = q;
+    }
+    return plan;
+}
+
 void serialize_plan(const fl_geom& g, const std::vector<fl_pass>& plan, std::vector<int>& out) {
     out.clear();
     out.push_back(g.C);

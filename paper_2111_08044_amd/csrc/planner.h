@@ -30,6 +30,11 @@ std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_
 // norm).
 std::vector<fl_pass> plan_cover(const fl_geom& g);
 
+// The same cover with each pass's bonds packed into register groups of g.R
+// consecutive tile bits: a group with first bit u0 holds the bonds on bits
+// (u0 + i, u0 + i + 1), i = 0 .. R-2 (op bit i, op slot = bond, no gate).
+std::vector<fl_pass> plan_cover_groups(const fl_geom& g);
+
 // Flatten a plan into int32 words (for inspection and host-side tests):
 // [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {opi, opg, ops}*}*}*]
 void serialize_plan(const fl_geom& g, const std::vector<fl_pass>& plan, std::vector<int>& out);

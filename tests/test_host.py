@@ -215,6 +215,39 @@ def test_energy_cover_visits_every_bond_once(dtype, L):
     assert sorted(seen) == list(range(L - 1))
 
 
+@pytest.mark.parametrize("L", [14, 15, 20, 25, 30, 34])
+def test_grouped_energy_cover_visits_every_bond_once(L):
+    """complex64 cover on 13-bit tiles: every bond exactly once, as op bit i of
+    a 5-bit register group inside the tile whose two bits are chain
+    neighbours; the first pass also reduces the norm.  At L = 30 the 29 bonds
+    take 4 passes (12 bonds in the first, then windows of 6 bonds)."""
+    C, W, R, passes = pt.parse_plan(fl.fl_plan_query(L, "c64", 6, 0, False))
+    assert (C, W, R) == (6, 7, 5)
+    seen = []
+    for k, (h, flags, groups) in enumerate(passes):
+        assert flags == (1 if k == 0 else 0)
+        rows = 0
+        for u0, ops in groups:
+            assert 0 <= u0 and u0 + R <= C + W and 1 <= len(ops) <= R - 1
+            for i, g, slot in ops:
+                assert 0 <= i <= R - 2 and g == -1
+                p, p1 = pt.phys_bit(u0 + i, C, h), pt.phys_bit(u0 + i + 1, C, h)
+                assert p1 == p + 1 and slot == L - 2 - p
+                seen.append(slot)
+            rows += len(ops)
+        assert rows <= C + W - 1
+    assert sorted(seen) == list(range(L - 1))
+    if L == 30:
+        assert len(passes) == 4 and sum(len(o) for _, o in passes[0][2]) == 12
+
+
+def test_grouped_energy_cover_needs_complex64_and_long_chains():
+    with pytest.raises(fl.FloquetError):
+        fl.fl_plan_query(13, "c64", 6, 0, False)
+    with pytest.raises(fl.FloquetError):
+        fl.fl_plan_query(20, "c128", 6, 0, False)
+
+
 def test_plan_statistics_L30():
     """The fused plan at L = 30 complex64 needs few passes per period: with the
     one-step lookahead of the planner, 31 passes for a 16-period block and 20
