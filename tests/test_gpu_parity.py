@@ -122,8 +122,11 @@ def test_small_chains_element_by_element(dtype, L):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("L", [2, 6, 13, 16, 21])
+@pytest.mark.parametrize("L", [2, 6, 13, 14, 16, 21])
 def test_rdm_energy_and_spread_match_oracle(dtype, L):
+    """Bond density matrices, energy, norm and spread against the oracle on a
+    random (non-product) state.  complex64 from L = 14 up runs the 13-bit-tile
+    register-group readout (L = 14: two tiles), below it the 12-bit forms."""
     say(f"case: rdm L={L} {dtype}")
     w, hs = _model(L, seed=7)
     rng = np.random.default_rng(L)
@@ -135,7 +138,7 @@ def test_rdm_energy_and_spread_match_oracle(dtype, L):
     E, N, rho = fl.fl_expect_energy(ctx, psi, rdm=True)
     Er, Nr = O.energy(vv, L, hs)
     # complex128: FP64 throughout.  complex64: products and per-tile partial
-    # sums (<= 2^12 terms, then a 64-lane tree) in FP32, FP64 across tiles;
+    # sums (<= 2^12 terms, 64-lane trees included) in FP32, FP64 across tiles;
     # rounding ~ 2^-24 * sqrt(terms) relative to the norm stays below 2e-7.
     rtol = 1e-13 if dtype == "c128" else 2e-7
     assert abs(N - Nr) < rtol * Nr
