@@ -74,11 +74,12 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo", "gue", "long"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue", "long", "sizes"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
                          "heating of the paper's GUE circuit versus drive frequency (gue), or the energy "
-                         "density every 100 periods of a long run (long, with --L 34)")
+                         "density every 100 periods of a long run (long, with --L 34), or time per "
+                         "period and per readout versus L = 16..34 (sizes)")
     ap.add_argument("--cpu-baseline-scaling", action="store_true",
                     help="only the cpu_baseline leg, at L = 20..28: the oracle's time per period and its "
                          "a L 2^L fit (no GPU)")
@@ -384,6 +385,39 @@ def long_run(fl, torch, L, nmax, every=100):
             "periods_per_s": round(n / wall, 3), "rows": rows}
 
 
+def size_scaling(fl, torch, Ls):
+    """Time per period of the plain complex64 sweep and of one energy readout
+    versus chain length (the cost the paper states grows as L 2^L, Sec. V):
+    16 periods after 16 warm-up periods per size, HIP events on the launch
+    stream."""
+    import floquet_inputs as fin
+    rows = []
+    for L in Ls:
+        w = fin.xyz_workload(L)
+        eng = fl.FloquetEngine(L, "c64")
+        eng.set_xyz(w["J"], w["fields"], w["T"])
+        psi = eng.new_state()
+        eng.init(psi, w["spinors"])
+        eng.step(psi, 16)
+        ev0, ev1, ev2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        stream = torch.cuda.current_stream()
+        ev0.record(stream)
+        eng.step(psi, 16)
+        ev1.record(stream)
+        e = eng.energy_density(psi)
+        ev2.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / 16
+        npass = plan_passes(fl, L, 16) / 16
+        rows.append({"L": L, "ms_per_period": round(ms, 4), "periods_per_s": round(1e3 / ms, 2),
+                     "passes_per_period": npass, "sweep_tflops": round(32.0 * (L - 1) * (1 << L) / (ms / 1e3) / 1e12, 2),
+                     "ms_energy_readout": round(ev1.elapsed_time(ev2), 3), "energy_density_32": e})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+        del psi, eng
+        torch.cuda.empty_cache()
+    return {"study": "sizes", "rows": rows}
+
+
 def l34_leg(fl, torch, periods=16):
     """L = 34 complex64 (128 GiB) in place: periods/s of the plain sweep and
     the energy density after the run."""
@@ -438,6 +472,9 @@ def main():
         return
     if args.study == "echo":
         print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
+        return
+    if args.study == "sizes":
+        print(json.dumps(size_scaling(fl, torch, list(range(16, 35, 2)))), flush=True)
         return
     if args.study == "long":
         print(json.dumps(long_run(fl, torch, L, args.max_periods)), flush=True)
