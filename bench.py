@@ -323,10 +323,15 @@ def gue_study(fl, torch, L, omegas, tmax, nrec=240):
 
         record(0)
         n, t0 = 0, time.perf_counter()
+        t_said = t0
         for r in recs:
             eng.step(psi, int(r - n))
             n = int(r)
             record(n)
+            if time.perf_counter() - t_said > 20.0:   # long runs report their progress
+                print(json.dumps({"omega": om, "period": n, "E_over_E0": round(E_s[-1] / E_s[0], 6)}),
+                      file=sys.stderr, flush=True)
+                t_said = time.perf_counter()
             if E_s[-1] / E_s[0] < np.exp(-2.5):
                 break
         torch.cuda.synchronize()
