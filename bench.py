@@ -585,6 +585,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_adjoint:
         out["adjoint"] = adjoint_ratio(fl, torch)
+        # the same ratio at L = 28 (2 GiB states; state, lambda and checkpoints far exceed the caches)
+        out["adjoint_L28"] = adjoint_ratio(fl, torch, L=28)
+        torch.cuda.empty_cache()
     if not args.no_l34:
         out["l34"] = l34_leg(fl, torch)
     if not args.no_cpu_baseline:
