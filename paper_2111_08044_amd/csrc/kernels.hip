@@ -873,16 +873,6 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
     }
 }
 
-// Bond reductions of complex64 states over full 13-bit tiles with 5-bit
-// register groups (the layout of the complex64 sweep): a cover pass's bonds
-// come packed into groups of R consecutive tile bits, every thread reads a
-// group's 2^R amplitudes from LDS once and forms the sums of all the group's
-// bonds from registers (8 quads per bond and thread), so each LDS word is read
-// once per group rather than once per bond.  Per tile, each lane sums its
-// quads in FP32, the wave sums the lanes in FP32 (512 quads), and the result
-// goes into FP64 per-wave LDS accumulators; the norm is summed in FP32 per
-// tile and in FP64 across tiles.  Persistent workgroups; partials as in
-// k_rdm_tiles.
 template <int A, int B, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
     if constexpr (A < B) {
@@ -891,6 +881,7 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Density-matrix sums of the bond on register bits (I, I+1) of a register group.
 template <int R, int I>
 __device__ __forceinline__ void group_bond_sums(const float (&vr)[1 << R], const float (&vi)[1 << R], float (&r)[16]) {
     // (immediate-operand markers keep the bit variants apart, as in apply_pair_g)
@@ -909,6 +900,16 @@ __device__ __forceinline__ void group_bond_sums(const float (&vr)[1 << R], const
     __asm__ volatile("; end bond sums on register bits %0" ::"i"(I));
 }
 
+// Bond reductions of complex64 states over full 13-bit tiles with 5-bit
+// register groups (the layout of the complex64 sweep): a cover pass's bonds
+// come packed into groups of R consecutive tile bits, every thread reads a
+// group's 2^R amplitudes from LDS once and forms the sums of all the group's
+// bonds from registers (8 quads per bond and thread), so each LDS word is read
+// once per group rather than once per bond.  Per tile, each lane sums its
+// quads in FP32, the wave sums the lanes in FP32 (512 quads), and the result
+// goes into FP64 per-wave LDS accumulators; the norm is summed in FP32 per
+// tile and in FP64 across tiles.  Persistent workgroups; partials as in
+// k_rdm_tiles.
 template <int R, int KT, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_rdm_groups(
     const float2* __restrict__ psi, int W, uint32_t ntiles, fl_pass pd, double* __restrict__ partials, int nslot) {
