@@ -89,6 +89,9 @@ def parse():
     ap.add_argument("--omegas", type=str, default="5,5.5,6,6.5,7,7.5,8",
                     help="drive frequencies of --study gue")
     ap.add_argument("--tmax", type=float, default=2e5, help="longest time (units of 1/J) of --study gue")
+    ap.add_argument("--echo-model", choices=["xyz", "gue"], default="xyz",
+                    help="circuit of --study echo: the XYZ+fields chain or the paper's GUE circuit")
+    ap.add_argument("--omega", type=float, default=8.0, help="drive frequency of --study echo --echo-model gue")
     ap.add_argument("--sweep-only", type=int, default=0, metavar="N",
                     help="only initialise the state and run N periods of the plain sweep, then exit "
                          "(a short program for hardware counter runs)")
@@ -271,26 +274,40 @@ def precision_study(fl, torch, L, nmax, variants=("plain", "dense6_fp32", "dense
             "ms_per_period": {k: round(v / t * 1e3, 3) for k, v in times.items()}}
 
 
-def echo_study(fl, torch, L, nmax):
+def echo_study(fl, torch, L, nmax, model="xyz", omega=8.0):
     """Echo of Sec. V: evolve d periods with U_F, then d with U_F^dagger, and
-    report |1 - <psi0|psi'0>| and the infidelity, complex64 plain sweep."""
+    report |1 - <psi0|psi'0>| and the infidelity, complex64 plain sweep.
+    model "xyz": the XYZ+fields chain from a product state; "gue": the paper's
+    GUE circuit at drive frequency omega from the ground state of H_o (the
+    paper's own echo setting, Sec. V)."""
     import floquet_inputs as fin
-    w = fin.xyz_workload(L)
     e = fl.FloquetEngine(L, "c64")
-    e.set_xyz(w["J"], w["fields"], w["T"])
     psi0, psi = e.new_state(), e.new_state()
-    e.init(psi0, w["spinors"])
+    if model == "gue":
+        e.set_paper_model(fin.gue_bond_sample(L), omega)
+        e.init_ground_pairs(psi0)
+    else:
+        w = fin.xyz_workload(L)
+        e.set_xyz(w["J"], w["fields"], w["T"])
+        e.init(psi0, w["spinors"])
     rows = []
     for d in _depths(nmax):
         psi.copy_(psi0)
-        e.step(psi, d)
-        e.step(psi, d, dagger=True)
+        for dagger in (False, True):
+            left = d
+            while left > 0:   # chunks, so that a long run reports its progress
+                k = min(left, 1000)
+                e.step(psi, k, dagger=dagger)
+                left -= k
+                if d > 1000:
+                    torch.cuda.synchronize()
+                    print(json.dumps({"t_f_periods": d, "dagger": dagger, "left": left}), file=sys.stderr, flush=True)
         ov, n0, n1 = e.overlap(psi0, psi)
         row = {"t_f_periods": d, "overlap_error": abs(1.0 - ov), "infidelity": 1.0 - abs(ov) ** 2 / (n0 * n1),
                "norm_minus_1": n1 - 1.0}
         rows.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
-    return {"study": "echo", "L": L, "rows": rows}
+    return {"study": "echo", "L": L, "model": model, "omega": omega if model == "gue" else None, "rows": rows}
 
 
 def gue_study(fl, torch, L, omegas, tmax, nrec=240):
@@ -476,7 +493,7 @@ def main():
         print(json.dumps(precision_study(fl, torch, L, args.max_periods, args.variants.split(","))), flush=True)
         return
     if args.study == "echo":
-        print(json.dumps(echo_study(fl, torch, L, args.max_periods)), flush=True)
+        print(json.dumps(echo_study(fl, torch, L, args.max_periods, args.echo_model, args.omega)), flush=True)
         return
     if args.study == "sizes":
         print(json.dumps(size_scaling(fl, torch, list(range(16, 35, 2)))), flush=True)
