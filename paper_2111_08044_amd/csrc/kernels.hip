@@ -351,25 +351,25 @@ __device__ __forceinline__ int pass_bit(const fl_pass& pd, int g, int q) {
 // all).  The next op's gate (32 scalar registers) is fetched while the
 // current one is applied; an explicit lgkmcnt(0) before each fetch waits for
 // the previous one, so that no wait inside an apply ever covers the fetch in
-// flight.
+// flight.  gc holds the group's first gate on entry and the next group's
+// first gate on return: that fetch overlaps the LDS exchange between the two
+// groups instead of stalling the start of the next group.
 template <typename T, int R, int SUB>
 __device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SUB][1 << R], const fl_pass& pd, int g,
-                                                const T* __restrict__ gates) {
+                                                const T* __restrict__ gates, T (&gc)[32]) {
     const int nops = pass_nops(pd, g);
-    T gc[32];
-    {
-        const T* G = gates + 32 * pass_gate(pd, g, 0);
-#pragma unroll
-        for (int k = 0; k < 32; ++k) gc[k] = G[k];
-    }
+    const int ng = pd.ngroups;
+    auto gate_of = [&](int q) {
+        const int idx = q < nops ? pass_gate(pd, g, q) : (g + 1 < ng ? pass_gate(pd, g + 1, 0) : pass_gate(pd, g, nops - 1));
+        return gates + 32 * idx;
+    };
     int i = pass_bit(pd, g, 0);
+    T g1[32];
     for (int q = 0; q < nops; q += 2) {
         __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
-        const int q1 = (q + 1 < nops) ? q + 1 : q;
-        const int i1 = pass_bit(pd, g, q1);
-        T g1[32];
+        const int i1 = pass_bit(pd, g, q + 1 < nops ? q + 1 : q);
         {
-            const T* G = gates + 32 * pass_gate(pd, g, q1);
+            const T* G = gate_of(q + 1);
 #pragma unroll
             for (int k = 0; k < 32; ++k) g1[k] = G[k];
         }
@@ -377,16 +377,19 @@ __device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SU
         for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gc);
         if (q + 1 < nops) {
             __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
-            const int q2 = (q + 2 < nops) ? q + 2 : q + 1;
-            i = pass_bit(pd, g, q2);
+            i = pass_bit(pd, g, q + 2 < nops ? q + 2 : q + 1);
             {
-                const T* G = gates + 32 * pass_gate(pd, g, q2);
+                const T* G = gate_of(q + 2);
 #pragma unroll
                 for (int k = 0; k < 32; ++k) gc[k] = G[k];
             }
 #pragma unroll
             for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i1, g1);
         }
+    }
+    if (nops & 1) {
+#pragma unroll
+        for (int k = 0; k < 32; ++k) gc[k] = g1[k];
     }
 }
 
@@ -541,11 +544,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
         }
     }
 
+    // the first gate of the pass (later groups find theirs fetched by the
+    // previous group's op loop)
+    T gx[32];
+    if (ng > 0) {
+        const T* G = gates + 32 * pass_gate(pd, 0, 0);
+#pragma unroll
+        for (int k = 0; k < 32; ++k) gx[k] = G[k];
+    }
     for (int g = 0; g < ng; ++g) {
         const int u0 = pass_u0(pd, g);
         if (g > 0 || din) lds_addrs(u0);
         if (g > 0) lds_to_regs();
-        sweep_group_ops<T, R, SUB>(vr, vi, pd, g, gates);
+        sweep_group_ops<T, R, SUB>(vr, vi, pd, g, gates, gx);
         if (g == ng - 1 && dout) break;
         regs_to_lds();
         __syncthreads();
