@@ -623,9 +623,15 @@ __device__ __forceinline__ void tr_steps_f32(float (&v)[N], int lane) {
                 const bool upper = (lane & D) != 0;
                 const float keep = upper ? v[k + H] : v[k];
                 const float send = upper ? v[k] : v[k + H];
+                // D = 8: row_ror:8 pairs lane i with i ^ 8.  D = 4:
+                // row_half_mirror pairs lane i with 7 - i in its run of 8; any
+                // pairing of the lanes with bit 2 clear to those with it set
+                // serves, the later steps sum over the whole run.
                 float got;
                 if constexpr (D == 8)
                     got = fl_dpp_f<0x128>(send);
+                else if constexpr (D == 4)
+                    got = fl_dpp_f<0x141>(send);
                 else
                     got = __shfl_xor(send, D);
                 v[k] = keep + got;
@@ -636,7 +642,7 @@ __device__ __forceinline__ void tr_steps_f32(float (&v)[N], int lane) {
         if constexpr (D >= 32) v[0] += __shfl_xor(v[0], 32);
         if constexpr (D >= 16) v[0] += __shfl_xor(v[0], 16);
         if constexpr (D >= 8) v[0] += fl_dpp_f<0x128>(v[0]);
-        if constexpr (D >= 4) v[0] += __shfl_xor(v[0], 4);
+        if constexpr (D >= 4) v[0] += fl_dpp_f<0x141>(v[0]);  // row_half_mirror: lane 7 - i of the run of 8
         if constexpr (D >= 2) v[0] += fl_dpp_f<0x4E>(v[0]);   // quad_perm(2,3,0,1): lane ^ 2
         if constexpr (D >= 1) v[0] += fl_dpp_f<0xB1>(v[0]);   // quad_perm(1,0,3,2): lane ^ 1
     }

@@ -342,7 +342,7 @@ def test_L30_echo_fp32():
 
 # ----------------------------------------------------------------- gradient
 
-@pytest.mark.parametrize("L,n,K", [(2, 3, 0), (5, 4, 2), (10, 20, 5), (13, 8, 4), (14, 6, 3)])
+@pytest.mark.parametrize("L,n,K", [(2, 3, 0), (5, 4, 2), (10, 20, 5), (13, 8, 4), (14, 6, 3), (16, 6, 3)])
 def test_gradient_fp64_matches_oracle_adjoint(L, n, K):
     say(f"case: grad fp64 L={L} n={n} K={K}")
     w, hs = _model(L, seed=31)
@@ -385,6 +385,28 @@ def test_gradient_fp32_L12_close_to_fp64():
     g = fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi))
     err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
     say(f"grad fp32 L=12: rel err {err:.3e}")
+    assert err < 1e-4
+
+
+def test_gradient_fp32_L16_close_to_fp64():
+    # 12-bit tiles with first and last register groups moved straight
+    # between HBM and registers as well as through LDS
+    L, n, K = 16, 12, 4
+    say("case: grad fp32 L=16")
+    w, hs = _model(L, seed=43)
+    gens = O.xyz_coupling_generators(L)
+    ref, _ = O.adjoint_gradient(L, hs, gens, w["T"], O.product_state(w["spinors"]), n)
+    ctx = fl.fl_create(L, "c64")
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ck = []
+    for _ in range(n // K):
+        ck.append(psi.clone())
+        fl.fl_apply_period(ctx, psi, K)
+    g = fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi))
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    say(f"grad fp32 L=16: rel err {err:.3e}")
     assert err < 1e-4
 
 
