@@ -410,6 +410,34 @@ def test_gradient_fp32_L16_close_to_fp64():
     assert err < 1e-4
 
 
+def test_gradient_fp32_L24_close_to_fp64_gpu():
+    # 4096 tiles of 12 bits: every workgroup of the complex64 reverse pass
+    # runs several tiles and copies the next one into LDS during the last
+    # register group; the complex128 reverse pass (the reference here) has
+    # no such copies.  Both start from the same product state.
+    L, n, K = 24, 8, 4
+    say("case: grad fp32 vs fp64 L=24")
+    w, hs = _model(L, seed=47)
+    gens = O.xyz_coupling_generators(L)
+    out = {}
+    for dt in ("c128", "c64"):
+        ctx = fl.fl_create(L, dt)
+        fl.fl_set_bonds(ctx, hs, w["T"])
+        psi = fl.new_state(ctx)
+        fl.fl_init_state(ctx, psi, w["spinors"])
+        ck = []
+        for _ in range(n // K):
+            ck.append(psi.clone())
+            fl.fl_apply_period(ctx, psi, K)
+        out[dt] = fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi))
+        del psi, ck
+        fl.fl_destroy(ctx)
+        torch.cuda.empty_cache()
+    err = np.max(np.abs(out["c64"] - out["c128"])) / np.max(np.abs(out["c128"]))
+    say(f"grad fp32 vs fp64 L=24: rel err {err:.3e}")
+    assert err < 1e-4
+
+
 def test_autograd_function_matches_oracle():
     L, n, K = 8, 12, 4
     w, hs = _model(L, seed=41)
