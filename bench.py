@@ -101,6 +101,46 @@ def parse():
     return ap.parse_args()
 
 
+def measured_ceilings(torch, psi):
+    """Ceilings measured on the device: the FP32 FMA rate of a plain FMA loop
+    (libflprobe.so, no packed FP32) and the bandwidth of a plain device copy of
+    the state (read + write), each the best of three, timed with events on the
+    current stream."""
+    import ctypes
+    out = {}
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lib_path = os.path.join(ROOT, "paper_2111_08044_amd", "libflprobe.so")
+    if os.path.exists(lib_path):
+        probe = ctypes.CDLL(lib_path)
+        probe.flp_fma_loop.restype = ctypes.c_int
+        probe.flp_fma_loop.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        blocks, iters = 256 * 32, 20000
+        buf = torch.empty(blocks * 256, dtype=torch.float32, device=psi.device)
+        best = 0.0
+        for _ in range(4):
+            ev0.record(stream)
+            rc = probe.flp_fma_loop(buf.data_ptr(), blocks, iters, ctypes.c_void_p(stream.cuda_stream))
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            if rc != 0:
+                raise RuntimeError(f"flp_fma_loop failed ({rc})")
+            best = max(best, 2.0 * 16 * iters * blocks * 256 / (ev0.elapsed_time(ev1) / 1e3) / 1e12)
+        out["fma_loop_tflops"] = round(best, 2)
+        del buf
+    tmp = torch.empty_like(psi)
+    best = 0.0
+    for _ in range(3):
+        ev0.record(stream)
+        tmp.copy_(psi)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        best = max(best, 2.0 * psi.numel() * psi.element_size() / (ev0.elapsed_time(ev1) / 1e3) / 1e9)
+    out["copy_gbps"] = round(best, 1)
+    del tmp
+    return out
+
+
 def plan_passes(fl, L, n):
     """Number of sweep launches the library runs for n periods (header word 3
     of the flattened plan)."""
@@ -562,6 +602,12 @@ def main():
             "hbm_gbps": round(achieved_gbps, 1), "hbm_frac": round(achieved_gbps / PEAK_HBM_GBPS, 4),
             "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4),
             "passes_per_period": launches / (nblk * reps), "gates_per_pass": gates / launches}
+    ceil = measured_ceilings(torch, psi)
+    if "fma_loop_tflops" in ceil:
+        roof["measured_fma_loop_tflops"] = ceil["fma_loop_tflops"]
+        roof["frac_of_measured_fma_loop"] = round(achieved_tflops / ceil["fma_loop_tflops"], 4)
+    roof["measured_copy_gbps"] = ceil["copy_gbps"]
+    roof["hbm_frac_of_measured_copy"] = round(achieved_gbps / ceil["copy_gbps"], 4)
 
     out = {
         "metric": METRIC, "value": round(periods_per_s, 3), "unit": "periods/s", "n_gpus": 1,

@@ -3,7 +3,8 @@
     python -m paper_2111_08044_amd.build        (from the repo root)
 
 Every source is compiled each call (objects go to a temporary folder), then
-linked into paper_2111_08044_amd/libfloquet.so.
+linked into paper_2111_08044_amd/libfloquet.so (the engine) and
+paper_2111_08044_amd/libflprobe.so (measurement probes).
 """
 from __future__ import annotations
 
@@ -21,6 +22,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfloquet.so")
 
 SOURCES = ["kernels.hip", "capi.cpp", "host_math.cpp", "planner.cpp"]
+# measurement probes (include/floquet_probe.h), a library of their own
+PROBE_SOURCES = ["probe.hip"]
+PROBE_LIB = os.path.join(PKG, "libflprobe.so")
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU ops.
 HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -51,14 +55,15 @@ def build(verbose: bool = False) -> str:
                 print(r.stderr, file=sys.stderr)
             return obj
 
-        with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-            objs = list(ex.map(compile_one, SOURCES))
-        out_tmp = LIB + ".tmp"
-        cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", out_tmp]
-        r = subprocess.run(cmd, capture_output=True, text=True)
-        if r.returncode != 0:
-            raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-        os.replace(out_tmp, LIB)
+        with ThreadPoolExecutor(max_workers=min(4, len(SOURCES) + len(PROBE_SOURCES))) as ex:
+            objs = list(ex.map(compile_one, SOURCES + PROBE_SOURCES))
+        for lib, lib_objs in ((LIB, objs[:len(SOURCES)]), (PROBE_LIB, objs[len(SOURCES):])):
+            out_tmp = lib + ".tmp"
+            cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", *lib_objs, "-o", out_tmp]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"link of {os.path.basename(lib)} failed:\n{r.stdout}\n{r.stderr}")
+            os.replace(out_tmp, lib)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     return LIB

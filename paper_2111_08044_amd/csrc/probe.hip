@@ -1,0 +1,31 @@
+// Measurement probes (libflprobe.so): the FP32 FMA ceiling of the vector ALUs.
+#include <hip/hip_runtime.h>
+
+#include "floquet.h"
+#include "floquet_probe.h"
+
+namespace {
+
+// 16 independent FMA chains per thread keep every SIMD issuing one FMA per
+// instruction slot; the fixed-point multiplier a < 1 keeps the values finite.
+__global__ __launch_bounds__(256) void k_fma_loop(float* __restrict__ out, int iters, float a, float b) {
+    float x[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = threadIdx.x * 1e-3f + k;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) x[k] = fmaf(x[k], a, b);
+    }
+    float s = 0.f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s += x[k];
+    out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
+}  // namespace
+
+extern "C" int flp_fma_loop(float* out, int blocks, int iters, void* hip_stream) {
+    if (!out || blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > 10000000) return FL_EINVAL;
+    hipLaunchKernelGGL(k_fma_loop, dim3(blocks), dim3(256), 0, (hipStream_t)hip_stream, out, iters, 0.999f, 1e-3f);
+    return hipGetLastError() == hipSuccess ? FL_OK : FL_EHIP;
+}
