@@ -453,6 +453,30 @@ def test_autograd_function_matches_oracle():
     assert abs(T.grad.item() - ref[-1]) < 1e-10
 
 
+# ----------------------------------------------------------------- measurement probe
+
+def test_fma_probe_computes_its_recurrence():
+    """The FMA-loop probe behind the bench's measured ceiling runs the
+    recurrence x <- 0.999 x + 0.001 it states (closed form in FP64)."""
+    import ctypes
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2111_08044_amd", "libflprobe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.flp_fma_loop
+    f.restype = ctypes.c_int
+    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    blocks, iters = 3, 500
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    assert f(out.data_ptr(), blocks, iters, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
+    torch.cuda.synchronize()
+    a, b = np.float64(np.float32(0.999)), np.float64(np.float32(1e-3))
+    t = np.arange(256, dtype=np.float64)
+    x0 = np.float32(t * 1e-3)[None, :].astype(np.float64) + np.arange(16, dtype=np.float64)[:, None]
+    ref = (a ** iters * x0 + b * (1 - a ** iters) / (1 - a)).sum(axis=0)
+    got = out.cpu().numpy().reshape(blocks, 256)
+    assert np.max(np.abs(got - ref[None, :]) / np.abs(ref)[None, :]) < 1e-4
+
+
 # ----------------------------------------------------------------- ABI errors
 
 def test_abi_error_paths_launch_nothing():
