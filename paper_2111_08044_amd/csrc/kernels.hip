@@ -3,14 +3,16 @@
 //  k_sweep_tiles / k_sweep
 //             fused gate sweep: one HBM read + write of the state applies
 //             every gate of a pass (Sec. II Eq. (2), fused as in Sec. II).
-//  k_rdm_tiles / k_rdm_win / k_rdm
+//  k_rdm_groups / k_rdm_tiles / k_rdm_win / k_rdm
 //             two-site reduced density matrices of the bonds of a pass (plus
 //             the norm), FP64 accumulation (Sec. II Eq. (1); Sec. IV Eq. (10)).
 //  k_apply_h  lambda = H0 psi, out of place (Sec. IV Eq. (11), Sec. V).
 //  k_adjoint  reverse replay with G^dagger and the overlap terms of the
 //             gradient of <H0>.
-//  k_dense6   pre-multiplied 6-qubit windows on the matrix cores (FP32 or
-//             split BF16x3, Sec. II on half-precision matrix units).
+//  k_dense6 / k_dense4
+//             pre-multiplied 6-qubit (FP32 or split BF16x3) and 4-qubit (FP32)
+//             windows on the matrix cores (Sec. II on half-precision matrix
+//             units).
 //  k_init     product initial state (Sec. IV Eq. (9) form; product of spinors).
 //  k_overlap  <phi|psi> and both norms across precisions (Sec. V echo measure).
 //  k_finalize deterministic sum of per-workgroup partials.
