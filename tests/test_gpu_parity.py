@@ -477,6 +477,33 @@ def test_fma_probe_computes_its_recurrence():
     assert np.max(np.abs(got - ref[None, :]) / np.abs(ref)[None, :]) < 1e-4
 
 
+# ----------------------------------------------------------------- degenerate depth
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_zero_periods_is_the_identity_and_gradient_is_explicit(dtype):
+    """n = 0: fl_apply_period leaves the state bit-identical; the gradient
+    then has only its explicit terms (Eq. (10) at t = 0), dE/dT = 0."""
+    L = 14
+    say(f"case: zero periods {dtype} L={L}")
+    w, hs = _model(L, seed=53)
+    ctx = fl.fl_create(L, dtype)
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    fl.fl_apply_period(ctx, psi, 3)
+    before = psi.clone()
+    fl.fl_apply_period(ctx, psi, 0)
+    fl.fl_apply_period(ctx, psi, 0, dagger=True)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(psi), torch.view_as_real(before))
+    gens = O.xyz_coupling_generators(L)
+    g = fl.fl_grad(ctx, psi, [], 0, 0, gens, torch.empty_like(psi))
+    ref, _ = O.adjoint_gradient(L, hs, gens, w["T"], psi.cpu().numpy().astype(np.complex128), 0)
+    tol = 1e-10 if dtype == "c128" else 1e-5
+    assert abs(g[-1]) < tol * max(1.0, np.max(np.abs(ref)))
+    assert np.max(np.abs(g - ref)) < tol * max(1.0, np.max(np.abs(ref)))
+
+
 # ----------------------------------------------------------------- ABI errors
 
 def test_abi_error_paths_launch_nothing():
