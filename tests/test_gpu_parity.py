@@ -282,6 +282,35 @@ def test_L34_in_place_lightcone_rdms_fp32():
         torch.cuda.empty_cache()
 
 
+def test_L33_complex128_in_place_lightcone_rdms():
+    """The largest complex128 chain (L = 33, 128 GiB in place): bond density
+    matrices after 2 periods against the oracle on light-cone subchains,
+    every bond, to FP64 rounding."""
+    L, n = 33, 2
+    free, total = torch.cuda.mem_get_info()
+    if free < (1 << L) * 16 + (8 << 30):
+        pytest.skip(f"needs 136 GiB of free device memory, {free / 2**30:.0f} GiB free")
+    say(f"case: L=33 complex128 light cone n={n}")
+    w, hs = _model(L)
+    G = O.floquet_gates(hs, w["T"])
+    ctx = fl.fl_create(L, "c128")
+    fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, w["J"], w["fields"]), w["T"])
+    psi = fl.new_state(ctx)
+    try:
+        fl.fl_init_state(ctx, psi, w["spinors"])
+        fl.fl_apply_period(ctx, psi, n)
+        E, N, rho = fl.fl_expect_energy(ctx, psi, rdm=True)
+        worst = 0.0
+        for b in range(L - 1):
+            worst = max(worst, np.max(np.abs(rho[b] - _lightcone_rdm(L, hs, G, w["spinors"], n, b))))
+        say(f"L=33 complex128 light-cone rdm worst {worst:.3e}, |N-1| {abs(N - 1):.3e}")
+        assert worst < 1e-12
+        assert abs(N - 1) < 1e-12
+    finally:
+        del psi
+        torch.cuda.empty_cache()
+
+
 def test_L30_swap_point_and_ising_closed_forms():
     """Closed forms at full size: the SWAP point permutes the spinors (pins
     layer order, bit order and tile mapping); the diagonal chain conserves E."""
