@@ -1137,6 +1137,27 @@ __global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ ps
     }
 }
 
+// complex64 form: a thread writes amplitudes x, x + 1 (x even, one 16-byte
+// store); they share the two high factors because the low table covers at
+// least one bit.  Same FP64 arithmetic per amplitude as k_init.
+__global__ __launch_bounds__(256) void k_init_pairs_c64(float4* __restrict__ psi2, const double2* __restrict__ tlo,
+                                                       const double2* __restrict__ tmid,
+                                                       const double2* __restrict__ thi, int a, int b, uint64_t n2) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t k = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n2; k += stride) {
+        const uint64_t x = 2 * k;
+        const double2 p = thi[x >> (a + b)], q = tmid[(x >> a) & ((1ull << b) - 1ull)];
+        const double2 r0 = tlo[x & ((1ull << a) - 1ull)], r1 = tlo[(x + 1) & ((1ull << a) - 1ull)];
+        const double pr = p.x * q.x - p.y * q.y, pi = p.x * q.y + p.y * q.x;
+        float4 o;
+        o.x = (float)(pr * r0.x - pi * r0.y);
+        o.y = (float)(pr * r0.y + pi * r0.x);
+        o.z = (float)(pr * r1.x - pi * r1.y);
+        o.w = (float)(pr * r1.y + pi * r1.x);
+        psi2[k] = o;
+    }
+}
+
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_overlap(const typename CT<TA>::c* __restrict__ a,
                                                  const typename CT<TB>::c* __restrict__ b, uint64_t n,
@@ -1780,7 +1801,11 @@ hipError_t launch_init(int dtype, void* psi, int L, const void* tabs, int a, int
     const double2* thi = tmid + (1 << b);
     const uint64_t want = (n + 255) / 256;
     const unsigned grid = (unsigned)(want < 65536 ? want : 65536);
-    if (dtype == 0)
+    if (dtype == 0 && a >= 1) {
+        const uint64_t want2 = (n / 2 + 255) / 256;
+        hipLaunchKernelGGL(k_init_pairs_c64, dim3((unsigned)(want2 < 65536 ? want2 : 65536)), dim3(256), 0, s,
+                           (float4*)psi, tlo, tmid, thi, a, b, n / 2);
+    } else if (dtype == 0)
         hipLaunchKernelGGL(k_init<float>, dim3(grid), dim3(256), 0, s, (float2*)psi, tlo, tmid, thi, a, b, n);
     else
         hipLaunchKernelGGL(k_init<double>, dim3(grid), dim3(256), 0, s, (double2*)psi, tlo, tmid, thi, a, b, n);
