@@ -311,11 +311,14 @@ def test_L33_complex128_in_place_lightcone_rdms():
         torch.cuda.empty_cache()
 
 
-def test_L30_swap_point_and_ising_closed_forms():
+@pytest.mark.parametrize("n", [5, 10, 16])
+def test_L30_swap_point_and_ising_closed_forms(n):
     """Closed forms at full size: the SWAP point permutes the spinors (pins
-    layer order, bit order and tile mapping); the diagonal chain conserves E."""
-    L, n = 30, 5
-    say("case: L=30 swap/ising")
+    layer order, bit order and tile mapping); the diagonal chain conserves E.
+    n = 10 and 16 run the benchmark's own plans (its 10-period step and its
+    16-period sweep block)."""
+    L = 30
+    say(f"case: L=30 swap/ising n={n}")
     w = fin.xyz_workload(L, seed=5)
     ctx = fl.fl_create(L, "c64")
     J = np.full_like(w["J"], 2 * np.pi)
