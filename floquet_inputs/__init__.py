@@ -86,3 +86,16 @@ def random_state(L: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     n = 1 << L
     return rng.standard_normal(n) + 1j * rng.standard_normal(n)
+
+
+def random_unitaries(count: int, dim: int, seed: int) -> np.ndarray:
+    """(count, dim, dim) complex128 Haar-random unitaries: QR of complex
+    Gaussian matrices with the phases of R's diagonal moved into Q."""
+    rng = np.random.default_rng(seed)
+    Z = rng.standard_normal((count, dim, dim)) + 1j * rng.standard_normal((count, dim, dim))
+    out = np.empty((count, dim, dim), dtype=np.complex128)
+    for k in range(count):
+        q, r = np.linalg.qr(Z[k])
+        d = np.diag(r)
+        out[k] = q * (d / np.abs(d))[None, :]
+    return out

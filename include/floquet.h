@@ -29,10 +29,20 @@
  *
  * Streams
  *   All device work is enqueued on the context's HIP stream (given at
- *   creation or by fl_set_stream).  Calls that return host values
+ *   creation or by fl_set_stream), in call order.  Uploads of parameters
+ *   (fl_set_bonds, fl_set_gates) and of initial-state tables (fl_init_state,
+ *   fl_init_pairs) are copied on that stream from pinned staging buffers the
+ *   context owns, so they take effect after every kernel enqueued before
+ *   them and before every kernel enqueued after them; these calls return
+ *   without waiting for the device (they block only when all four staging
+ *   buffers still feed copies that have not run).  When fl_set_stream
+ *   changes the stream, work enqueued afterwards waits for the work already
+ *   enqueued on the previous stream.  Calls that return host values
  *   (fl_expect_energy, fl_overlap, fl_energy_spread, fl_grad) synchronise
- *   that stream before returning; the others return immediately.
- *
+ *   the stream before returning.  A dense variant rebuilds its window plans
+ *   when the gates change and synchronises the stream then, before it frees
+ *   the old ones.
+
  * Errors
  *   Every int-returning call returns FL_OK (0) or a negative code; arguments
  *   are validated before anything is enqueued, so on FL_EINVAL / FL_ESTATE
@@ -83,20 +93,25 @@ int fl_set_stream(fl_ctx *ctx, void *hip_stream);
 /* Set the bond Hamiltonians and the period (Sec. III A, Eq. (5)).
  * h: host array [L-1][4][4] complex (double re, im), each Hermitian.
  * T: drive period (> 0).  Builds G_b = exp(-i (T/2) h_b) and G_b^dagger in
- * FP64 on the host and uploads them rounded to the context's precision.
+ * FP64 on the host and uploads them rounded to the context's precision, in
+ * stream order (see Streams).
  * Errors: FL_EINVAL (NULL, non-finite or non-Hermitian h, T <= 0), FL_EHIP. */
 int fl_set_bonds(fl_ctx *ctx, const double *h, double T);
 
-/* Test hook: install FP64 gates G [L-1][4][4] (complex, must be unitary) and,
- * optionally, the bond Hamiltonians h [L-1][4][4] used by the energy
- * (h may be NULL, then fl_expect_energy reports <H0> = 0).  The period is
- * recorded as T (used only by fl_grad). */
+/* Test hook: install FP64 gates G [L-1][4][4] (complex) and, optionally, the
+ * bond Hamiltonians h [L-1][4][4] used by the energy (h may be NULL, then
+ * fl_expect_energy reports <H0> = 0).  The period is recorded as T (used only
+ * by fl_grad).  Errors: FL_EINVAL (NULL G, non-finite entries, a gate with
+ * max |G^dagger G - I| > 1e-10, a non-Hermitian h), FL_EHIP. */
 int fl_set_gates(fl_ctx *ctx, const double *G, const double *h, double T);
 
 /* Write the product state psi[x] = prod_j s_j[bit_j(x)] (the form of the
  * initial state of Sec. IV, Eq. (9)), computed in FP64 and rounded.
  * psi: device, 2^L amplitudes of the context dtype.  spinors: host
- * [L][2] complex (double re, im), site-major.  Asynchronous. */
+ * [L][2] complex (double re, im), site-major.  Asynchronous: the factor
+ * tables go through a staging buffer (see Streams), the host does not wait.
+ * Errors: FL_EINVAL (NULL, misaligned or non-device psi, non-finite
+ * spinors), FL_EHIP. */
 int fl_init_state(fl_ctx *ctx, void *psi, const double *spinors);
 
 /* Write the pair-product state of Sec. IV, Eq. (9): the sites (2m, 2m+1)
@@ -107,7 +122,8 @@ int fl_init_state(fl_ctx *ctx, void *psi, const double *spinors);
  * the last site is unpaired and carries the spinor tail.  FP64, rounded.
  * psi: device, 2^L amplitudes of the context dtype.  pairs: host [L/2][4]
  * complex; tail: host [2] complex, required for odd L, ignored for even L.
- * Errors: FL_EINVAL (NULL, non-finite), FL_EHIP.  Asynchronous. */
+ * Errors: FL_EINVAL (NULL, non-finite), FL_EHIP.  Asynchronous, as
+ * fl_init_state. */
 int fl_init_pairs(fl_ctx *ctx, void *psi, const double *pairs, const double *tail);
 
 /* psi <- U_F^n psi (dagger = 0) or psi <- (U_F^dagger)^n psi (dagger = 1),

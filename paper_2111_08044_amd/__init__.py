@@ -116,12 +116,14 @@ def new_state(ctx: Context):
 
 def fl_set_bonds(ctx: Context, h, T: float):
     hb = _c16(h, (ctx.L - 1, 4, 4))
+    _stream(ctx)
     check(lib().fl_set_bonds(ctx.handle, _dp(hb), float(T)))
 
 
 def fl_set_gates(ctx: Context, G, h=None, T: float = 0.0):
     Gb = _c16(G, (ctx.L - 1, 4, 4))
     hb = _c16(h, (ctx.L - 1, 4, 4)) if h is not None else None
+    _stream(ctx)
     check(lib().fl_set_gates(ctx.handle, _dp(Gb), _dp(hb) if hb is not None else None, float(T)))
 
 

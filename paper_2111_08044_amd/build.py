@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfloquet.so")
 
 SOURCES = ["kernels.hip", "capi.cpp", "host_math.cpp", "planner.cpp"]
-# measurement probes (include/floquet_probe.h), a library of their own
+# measurement probes (csrc/probe.h), a library of their own
 PROBE_SOURCES = ["probe.hip"]
 PROBE_LIB = os.path.join(PKG, "libflprobe.so")
 

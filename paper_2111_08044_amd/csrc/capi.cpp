@@ -46,6 +46,8 @@ constexpr int kPlanBlock = 16;        // periods per planned block
 constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
+constexpr int kStageSlots = 4;        // pinned host staging slots for uploads
+constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 complex doubles (init tables)
 
 int kmax_of(int dtype) { return dtype == FL_C64 ? FL_KMAX_C64 : FL_KMAX_C128; }
 size_t amp_bytes(int dtype) { return dtype == FL_C64 ? 8 : 16; }
@@ -66,6 +68,14 @@ struct fl_ctx {
     double* h_red = nullptr;   // pinned host copy
     void* d_tabs = nullptr;    // product-state factor tables
     double* d_mpart = nullptr; // gradient partials [kAdjGrid][L-1][16]
+    // Uploads (gates, bond terms, init tables) are copied on the context
+    // stream from pinned staging slots; slot k may be refilled once the copy
+    // recorded by stage_ev[k] has run.
+    unsigned char* h_stage = nullptr;
+    hipEvent_t stage_ev[kStageSlots] = {};
+    bool stage_used[kStageSlots] = {};
+    int stage_next = 0;
+    hipEvent_t ev_switch = nullptr;    // orders work across a change of stream
     std::map<std::pair<int, int>, std::vector<fl_pass>> plans;
     std::map<int, std::vector<fl_pass>> adj_plans;
     struct DensePlan {
@@ -73,6 +83,7 @@ struct fl_ctx {
         void* d_mats = nullptr;        // 64 KiB of MFMA fragments per window
     };
     std::map<std::pair<int, int>, DensePlan> dense_plans;
+    std::vector<std::vector<unsigned char>> dense_host;  // host fragments: sources of in-flight uploads
     std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
     std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
     std::vector<fl_win> cover_win;    // per cover_rdm pass: window-bond form (h < 0: not eligible)
@@ -125,31 +136,65 @@ bool finite_all(const double* a, size_t n) {
     return true;
 }
 
-// Round FP64 complex matrices to the context precision, 32 reals per 4x4.
+// Next pinned staging slot, once the upload that last read it has run.
+int stage_slot(fl_ctx* c, unsigned char** out, int* slot) {
+    const int k = c->stage_next;
+    c->stage_next = (k + 1) % kStageSlots;
+    if (c->stage_used[k]) FL_HIP(hipEventSynchronize(c->stage_ev[k]));
+    *out = c->h_stage + (size_t)k * kStageBytes;
+    *slot = k;
+    return FL_OK;
+}
+
+// Copy `bytes` of staged data to dst on the context stream and mark the slot busy.
+int stage_upload(fl_ctx* c, int slot, void* dst, size_t bytes) {
+    FL_HIP(hipMemcpyAsync(dst, c->h_stage + (size_t)slot * kStageBytes, bytes, hipMemcpyHostToDevice, c->stream));
+    FL_HIP(hipEventRecord(c->stage_ev[slot], c->stream));
+    c->stage_used[slot] = true;
+    return FL_OK;
+}
+
+// Round FP64 complex matrices to the context precision, 32 reals per 4x4,
+// and upload them in stream order (after every kernel already enqueued).
 int upload_mats(fl_ctx* c, void* dst, const std::vector<cd>& m, size_t nmat) {
+    unsigned char* buf = nullptr;
+    int slot = 0;
+    int rc = stage_slot(c, &buf, &slot);
+    if (rc) return rc;
+    size_t bytes = 0;
     if (c->dtype == FL_C64) {
-        std::vector<float> t(nmat * 32);
+        float* t = reinterpret_cast<float*>(buf);
         for (size_t i = 0; i < nmat * 16; ++i) {
             t[2 * i] = (float)m[i].real();
             t[2 * i + 1] = (float)m[i].imag();
         }
-        FL_HIP(hipMemcpy(dst, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice));
+        bytes = nmat * 32 * sizeof(float);
     } else {
-        std::vector<double> t(nmat * 32);
+        double* t = reinterpret_cast<double*>(buf);
         for (size_t i = 0; i < nmat * 16; ++i) {
             t[2 * i] = m[i].real();
             t[2 * i + 1] = m[i].imag();
         }
-        FL_HIP(hipMemcpy(dst, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+        bytes = nmat * 32 * sizeof(double);
     }
+    return stage_upload(c, slot, dst, bytes);
+}
+
+// Drop the dense window plans; kernels already enqueued may still read them.
+int drop_dense_plans(fl_ctx* c) {
+    if (c->dense_plans.empty() && c->dense_host.empty()) return FL_OK;
+    FL_HIP(hipStreamSynchronize(c->stream));
+    for (auto& kv : c->dense_plans)
+        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
+    c->dense_plans.clear();
+    c->dense_host.clear();
     return FL_OK;
 }
 
 int install_gates(fl_ctx* c) {
     const int nb = c->L - 1;
-    for (auto& kv : c->dense_plans)
-        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
-    c->dense_plans.clear();
+    int rc0 = drop_dense_plans(c);
+    if (rc0) return rc0;
     std::vector<cd> both((size_t)2 * nb * 16);
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 4; ++i)
@@ -255,9 +300,13 @@ int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
     if (nwin) {
         hipError_t e = hipMalloc(&dp.d_mats, frags.size());
         if (e != hipSuccess) return fail(FL_ENOMEM, "window matrices: device allocation failed");
-        e = hipMemcpy(dp.d_mats, frags.data(), frags.size(), hipMemcpyHostToDevice);
+        // stream-ordered; the host copy lives as long as the plan
+        c->dense_host.push_back(std::move(frags));
+        const auto& src = c->dense_host.back();
+        e = hipMemcpyAsync(dp.d_mats, src.data(), src.size(), hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) {
             (void)hipFree(dp.d_mats);
+            c->dense_host.pop_back();
             return fail_hip(e, "window matrices upload");
         }
     }
@@ -339,6 +388,30 @@ int apply_h0(fl_ctx* c, const void* psi, void* out) {
     return FL_OK;
 }
 
+// Stage the three product-state factor tables, copy them to d_tabs and
+// launch the init kernel, all in stream order (no host wait).
+int upload_tables_and_init(fl_ctx* c, void* psi, const std::vector<cd>& tlo, const std::vector<cd>& tmid,
+                           const std::vector<cd>& thi, int a, int b) {
+    const size_t n = tlo.size() + tmid.size() + thi.size();
+    if (n * 2 * sizeof(double) > kStageBytes || n > (size_t)3 * 4096) return fail(FL_EINVAL, "internal: init tables too large");
+    unsigned char* buf = nullptr;
+    int slot = 0;
+    int rc = stage_slot(c, &buf, &slot);
+    if (rc) return rc;
+    double* t = reinterpret_cast<double*>(buf);
+    size_t k = 0;
+    for (const std::vector<cd>* v : {&tlo, &tmid, &thi})
+        for (const cd& z : *v) {
+            t[k++] = z.real();
+            t[k++] = z.imag();
+        }
+    rc = stage_upload(c, slot, c->d_tabs, k * sizeof(double));
+    if (rc) return rc;
+    hipError_t e = fl::launch_init(c->dtype, psi, c->L, c->d_tabs, a, b, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_init launch");
+    return FL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -413,6 +486,10 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_red, (size_t)2 * L * 16 * sizeof(double), 0);
     if (e == hipSuccess) e = hipMalloc(&c->d_tabs, (size_t)3 * 4096 * 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_mpart, (size_t)kAdjGrid * nb * 16 * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_stage, (size_t)kStageSlots * kStageBytes, 0);
+    for (int k = 0; k < kStageSlots && e == hipSuccess; ++k)
+        e = hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_switch, hipEventDisableTiming);
     if (e != hipSuccess) {
         fl_destroy(c);
         (void)hipGetLastError();
@@ -424,6 +501,12 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
 
 int fl_destroy(fl_ctx* c) {
     if (!c) return FL_OK;
+    // kernels and uploads still in flight read the buffers freed below
+    (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < kStageSlots; ++k)
+        if (c->stage_ev[k]) (void)hipEventDestroy(c->stage_ev[k]);
+    if (c->ev_switch) (void)hipEventDestroy(c->ev_switch);
+    if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->d_gates) (void)hipFree(c->d_gates);
     if (c->d_h) (void)hipFree(c->d_h);
     if (c->d_part) (void)hipFree(c->d_part);
@@ -439,7 +522,14 @@ int fl_destroy(fl_ctx* c) {
 
 int fl_set_stream(fl_ctx* c, void* hip_stream) {
     if (!c) return fail(FL_EINVAL, "ctx is NULL");
-    c->stream = (hipStream_t)hip_stream;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (s == c->stream) return FL_OK;
+    // The context's own buffers (gate tables, reduction scratch, init
+    // tables) are reused across calls: work on the new stream starts after
+    // everything already enqueued on the old one.
+    FL_HIP(hipEventRecord(c->ev_switch, c->stream));
+    FL_HIP(hipStreamWaitEvent(s, c->ev_switch, 0));
+    c->stream = s;
     return FL_OK;
 }
 
@@ -479,16 +569,34 @@ int fl_set_gates(fl_ctx* c, const double* G, const double* h, double T) {
     const int nb = c->L - 1;
     if (!finite_all(G, (size_t)nb * 32) || (h && !finite_all(h, (size_t)nb * 32)))
         return fail(FL_EINVAL, "non-finite entries");
-    c->G.assign((size_t)nb * 16, cd(0));
-    for (int b = 0; b < nb; ++b) read_c16(G + (size_t)b * 32, &c->G[(size_t)b * 16]);
-    if (h) {
-        c->h.assign((size_t)nb * 16, cd(0));
-        for (int b = 0; b < nb; ++b) read_c16(h + (size_t)b * 32, &c->h[(size_t)b * 16]);
-        c->have_h = true;
-    } else {
-        c->h.assign((size_t)nb * 16, cd(0));
-        c->have_h = true;
+    std::vector<cd> Gv((size_t)nb * 16);
+    for (int b = 0; b < nb; ++b) read_c16(G + (size_t)b * 32, &Gv[(size_t)b * 16]);
+    for (int b = 0; b < nb; ++b) {
+        const cd* m = &Gv[(size_t)b * 16];
+        double dev = 0.0;  // max |G^dagger G - I|
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+                cd s = 0.0;
+                for (int k = 0; k < 4; ++k) s += std::conj(m[4 * k + i]) * m[4 * k + j];
+                dev = std::max(dev, std::abs(s - (i == j ? 1.0 : 0.0)));
+            }
+        if (dev > 1e-10) return fail(FL_EINVAL, "G[" + std::to_string(b) + "] is not unitary");
     }
+    if (h) {
+        for (int b = 0; b < nb; ++b)
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    const cd hij(h[(size_t)b * 32 + 2 * (4 * i + j)], h[(size_t)b * 32 + 2 * (4 * i + j) + 1]);
+                    const cd hji(h[(size_t)b * 32 + 2 * (4 * j + i)], h[(size_t)b * 32 + 2 * (4 * j + i) + 1]);
+                    if (std::abs(hij - std::conj(hji)) > 1e-12 * std::max(1.0, std::abs(hij)))
+                        return fail(FL_EINVAL, "h[" + std::to_string(b) + "] is not Hermitian");
+                }
+    }
+    c->G = Gv;
+    c->h.assign((size_t)nb * 16, cd(0));
+    if (h)
+        for (int b = 0; b < nb; ++b) read_c16(h + (size_t)b * 32, &c->h[(size_t)b * 16]);
+    c->have_h = true;
     c->T = T;
     int rc = install_gates(c);
     if (rc) return rc;
@@ -508,18 +616,7 @@ int fl_init_state(fl_ctx* c, void* psi, const double* spinors) {
     const int a = std::min(L, 12), b = std::min(L - a, 12);
     std::vector<cd> tlo, tmid, thi;
     fl::product_tables(L, s.data(), a, b, tlo, tmid, thi);
-    std::vector<double> buf;
-    for (auto* t : {&tlo, &tmid, &thi})
-        for (const cd& z : *t) {
-            buf.push_back(z.real());
-            buf.push_back(z.imag());
-        }
-    FL_HIP(hipMemcpyAsync(c->d_tabs, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipError_t e = fl::launch_init(c->dtype, psi, L, c->d_tabs, a, b, c->stream);
-    if (e != hipSuccess) return fail_hip(e, "k_init launch");
-    // the host staging buffer must outlive the asynchronous copy
-    FL_HIP(hipStreamSynchronize(c->stream));
-    return FL_OK;
+    return upload_tables_and_init(c, psi, tlo, tmid, thi, a, b);
 }
 
 int fl_init_pairs(fl_ctx* c, void* psi, const double* pairs, const double* tail) {
@@ -544,17 +641,7 @@ int fl_init_pairs(fl_ctx* c, void* psi, const double* pairs, const double* tail)
     std::vector<cd> tlo, tmid, thi;
     if (!fl::pair_tables(L, pv.data(), tv.data(), a, b, tlo, tmid, thi))
         return fail(FL_EINVAL, "internal: pair table boundary");
-    std::vector<double> buf;
-    for (auto* t : {&tlo, &tmid, &thi})
-        for (const cd& z : *t) {
-            buf.push_back(z.real());
-            buf.push_back(z.imag());
-        }
-    FL_HIP(hipMemcpyAsync(c->d_tabs, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    hipError_t e = fl::launch_init(c->dtype, psi, L, c->d_tabs, a, b, c->stream);
-    if (e != hipSuccess) return fail_hip(e, "k_init launch");
-    FL_HIP(hipStreamSynchronize(c->stream));
-    return FL_OK;
+    return upload_tables_and_init(c, psi, tlo, tmid, thi, a, b);
 }
 
 int fl_apply_period(fl_ctx* c, void* psi, int64_t n, int dagger) {

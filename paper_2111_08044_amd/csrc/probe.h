@@ -1,5 +1,5 @@
 /*
- * floquet_probe.h -- measurement probes that sit beside the engine (libflprobe.so).
+ * probe.h -- measurement probes that sit beside the engine (libflprobe.so).
  *
  * Not part of the method.  The complex64 sweep is bound by FP32 vector FMAs
  * (16 per amplitude and gate, Sec. III A's gate application written out as

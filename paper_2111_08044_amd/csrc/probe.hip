@@ -2,7 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include "floquet.h"
-#include "floquet_probe.h"
+#include "probe.h"
 
 namespace {
 

@@ -14,10 +14,12 @@ class FloquetEngine:
     def __init__(self, L: int, dtype: str = "c64", variant: str = "plain"):
         self.L = L
         self.ctx = fl_create(L, dtype, variant)
+        self.generation = 0   # bumped by every change of the gates
 
     def set_bonds(self, h, T: float):
         self.h = np.asarray(h, dtype=np.complex128).reshape(self.L - 1, 4, 4).copy()
         fl_set_bonds(self.ctx, self.h, T)
+        self.generation += 1
 
     def set_paper_model(self, Hk, omega: float):
         """The paper's circuit (Sec. III A): gates exp(-i H_k T), T = 2 pi / omega,
@@ -116,12 +118,26 @@ class FloquetEnergy:
     """E_n(J, T) = <psi_n|H0|psi_n> of the XYZ-plus-fields chain as a
     differentiable torch function of the couplings J (L-1, 3) and the period T.
 
-    forward evolves on the GPU, storing the state every K periods; backward
-    runs the library's reverse pass (G^dagger replay from those checkpoints).
-    Each forward supports one backward (the saved state is consumed).
+    forward evolves on the GPU, storing the state every K periods (K = 0: no
+    checkpoints); n must be a multiple of K.  backward runs the library's
+    reverse pass (G^dagger replay from those checkpoints) with the couplings,
+    fields and period its own forward used: if the engine's gates changed in
+    between (another forward, set_bonds, set_xyz), they are installed again
+    first.  Each forward supports one backward (the saved state is consumed).
 
         E = FloquetEnergy.apply(J, T, engine, fields, spinors, n, K)
     """
+
+    @staticmethod
+    def check_depth(n, K):
+        """The checkpoint schedule of Sec. V's reverse replay: states at
+        periods 0, K, ..., n - K, so K must divide n (K = 0: none)."""
+        n, K = int(n), int(K)
+        if n < 0 or K < 0:
+            raise ValueError(f"n = {n} and K = {K} must be >= 0")
+        if K > 0 and n % K != 0:
+            raise ValueError(f"n = {n} is not a multiple of the checkpoint interval K = {K}")
+        return n, K
 
     @staticmethod
     def _fn():
@@ -130,9 +146,14 @@ class FloquetEnergy:
         class _F(torch.autograd.Function):
             @staticmethod
             def forward(ctx, J, T, engine, fields, spinors, n, K):
+                n, K = FloquetEnergy.check_depth(n, K)
                 L = engine.L
-                Jn = J.detach().cpu().numpy().astype(np.float64)
-                engine.set_xyz(Jn, fields, float(T))
+                Jn = J.detach().cpu().numpy().astype(np.float64).copy()
+                fn = np.array(fields, dtype=np.float64, copy=True)
+                Tn = float(T)
+                engine.set_xyz(Jn, fn, Tn)
+                ctx.params = (Jn, fn, Tn)
+                ctx.generation = engine.generation
                 psi = engine.new_state()
                 engine.init(psi, spinors)
                 ckpts = []
@@ -149,6 +170,10 @@ class FloquetEnergy:
             @staticmethod
             def backward(ctx, gE):
                 eng = ctx.engine
+                if ctx.psi is None:
+                    raise RuntimeError("FloquetEnergy: backward ran twice on one forward (its saved state is consumed)")
+                if eng.generation != ctx.generation:
+                    eng.set_xyz(*ctx.params)
                 lam = torch.empty_like(ctx.psi)
                 g = fl_grad(eng.ctx, ctx.psi, ctx.ckpts, ctx.n, ctx.K, fl_xyz_generators(ctx.L), lam)
                 ctx.psi = ctx.ckpts = None
@@ -160,4 +185,5 @@ class FloquetEnergy:
 
     @classmethod
     def apply(cls, J, T, engine, fields, spinors, n, K):
+        cls.check_depth(n, K)
         return cls._fn().apply(J, T, engine, fields, spinors, n, K)

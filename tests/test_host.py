@@ -38,13 +38,13 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_probe_library_exports_and_validates():
-    """libflprobe.so exports what include/floquet_probe.h declares and rejects
+    """libflprobe.so exports what csrc/probe.h declares and rejects
     bad arguments before launching anything."""
     import ctypes
     path = os.path.join(ROOT, "paper_2111_08044_amd", "libflprobe.so")
     if not os.path.exists(path):
         pytest.skip("libflprobe.so not built")
-    with open(os.path.join(ROOT, "include", "floquet_probe.h")) as f:
+    with open(os.path.join(ROOT, "paper_2111_08044_amd", "csrc", "probe.h")) as f:
         names = set(re.findall(r"^\s*int\s*(flp_\w+)\s*\(", f.read(), re.M))
     assert names == {"flp_fma_loop"}
     lib = ctypes.CDLL(path)
@@ -176,7 +176,7 @@ def test_tile_map_is_a_permutation_with_the_right_bits(dtype, L):
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("L", [2, 3, 4, 5, 8, 12, 13, 14, 15, 19, 24, 30, 34])
-@pytest.mark.parametrize("n", [1, 2, 5, 16, 17, 40])
+@pytest.mark.parametrize("n", [1, 2, 5, 8, 10, 16, 17, 40])
 @pytest.mark.parametrize("dagger", [False, True])
 def test_sweep_plan_is_the_brickwork_circuit(dtype, L, n, dagger):
     if dtype == "c128" and L == 34:
