@@ -46,7 +46,7 @@ constexpr int kPlanBlock = 16;        // periods per planned block
 constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
-constexpr int kStageSlots = 4;        // pinned host staging slots for uploads
+constexpr int kStageSlots = 8;        // pinned host staging slots for uploads
 constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 complex doubles (init tables)
 
 int kmax_of(int dtype) { return dtype == FL_C64 ? FL_KMAX_C64 : FL_KMAX_C128; }
@@ -63,6 +63,7 @@ struct fl_ctx {
     std::vector<cd> h, G;  // FP64, (L-1) x 16
     void* d_gates = nullptr;   // 2 (L-1) gates, 32 reals each, context precision
     void* d_h = nullptr;       // (L-1) bond Hamiltonians, 32 reals each
+    double* d_h64 = nullptr;   // the same in FP64 (energy contraction on the device)
     double* d_part = nullptr;  // reduction partials [kReduceGrid][L][16]
     double* d_red = nullptr;   // finalized reductions, 2 x L x 16
     double* h_red = nullptr;   // pinned host copy
@@ -86,7 +87,6 @@ struct fl_ctx {
     std::vector<std::vector<unsigned char>> dense_host;  // host fragments: sources of in-flight uploads
     std::vector<fl_pass> cover;       // bond cover of the sweep geometry (H0 psi)
     std::vector<fl_pass> cover_rdm;   // bond cover of the reduction geometry
-    std::vector<fl_win> cover_win;    // per cover_rdm pass: window-bond form (h < 0: not eligible)
     bool use_grp = false;             // complex64, L >= 14: the reductions run on 13-bit tiles
     fl_geom geom_grp{};               // (L, 13, 5)
     std::vector<fl_pass> cover_grp;   // bond cover of geom_grp in register groups
@@ -146,38 +146,51 @@ int stage_slot(fl_ctx* c, unsigned char** out, int* slot) {
     return FL_OK;
 }
 
-// Copy `bytes` of staged data to dst on the context stream and mark the slot busy.
-int stage_upload(fl_ctx* c, int slot, void* dst, size_t bytes) {
-    FL_HIP(hipMemcpyAsync(dst, c->h_stage + (size_t)slot * kStageBytes, bytes, hipMemcpyHostToDevice, c->stream));
-    FL_HIP(hipEventRecord(c->stage_ev[slot], c->stream));
-    c->stage_used[slot] = true;
-    return FL_OK;
-}
-
-// Round FP64 complex matrices to the context precision, 32 reals per 4x4,
-// and upload them in stream order (after every kernel already enqueued).
-int upload_mats(fl_ctx* c, void* dst, const std::vector<cd>& m, size_t nmat) {
+// One staged upload: up to three (device destination, bytes) copies from
+// consecutive regions of one staging slot, then the slot's event.
+struct Staged {
     unsigned char* buf = nullptr;
     int slot = 0;
-    int rc = stage_slot(c, &buf, &slot);
-    if (rc) return rc;
-    size_t bytes = 0;
-    if (c->dtype == FL_C64) {
-        float* t = reinterpret_cast<float*>(buf);
+    size_t used = 0;
+    void* dst[3] = {};
+    size_t off[3] = {}, len[3] = {};
+    int n = 0;
+};
+
+// Round FP64 complex matrices to `real_bytes` (4: FP32, 8: FP64) reals, 32 per
+// 4x4, into the next region of the staged upload.
+void stage_mats(Staged& st, void* dst, const std::vector<cd>& m, size_t nmat, int real_bytes) {
+    unsigned char* p = st.buf + st.used;
+    if (real_bytes == 4) {
+        float* t = reinterpret_cast<float*>(p);
         for (size_t i = 0; i < nmat * 16; ++i) {
             t[2 * i] = (float)m[i].real();
             t[2 * i + 1] = (float)m[i].imag();
         }
-        bytes = nmat * 32 * sizeof(float);
     } else {
-        double* t = reinterpret_cast<double*>(buf);
+        double* t = reinterpret_cast<double*>(p);
         for (size_t i = 0; i < nmat * 16; ++i) {
             t[2 * i] = m[i].real();
             t[2 * i + 1] = m[i].imag();
         }
-        bytes = nmat * 32 * sizeof(double);
     }
-    return stage_upload(c, slot, dst, bytes);
+    const size_t bytes = nmat * 32 * (size_t)real_bytes;
+    st.dst[st.n] = dst;
+    st.off[st.n] = st.used;
+    st.len[st.n] = bytes;
+    ++st.n;
+    st.used += (bytes + 255) & ~(size_t)255;
+}
+
+// Enqueue the staged copies on the context stream (after every kernel already
+// enqueued) and mark the slot busy until they have run.
+int stage_commit(fl_ctx* c, const Staged& st) {
+    if (st.used > kStageBytes) return fail(FL_EINVAL, "internal: staged upload too large");
+    for (int k = 0; k < st.n; ++k)
+        FL_HIP(hipMemcpyAsync(st.dst[k], st.buf + st.off[k], st.len[k], hipMemcpyHostToDevice, c->stream));
+    FL_HIP(hipEventRecord(c->stage_ev[st.slot], c->stream));
+    c->stage_used[st.slot] = true;
+    return FL_OK;
 }
 
 // Drop the dense window plans; kernels already enqueued may still read them.
@@ -191,10 +204,12 @@ int drop_dense_plans(fl_ctx* c) {
     return FL_OK;
 }
 
+// Gates and G^dagger in the context precision, the bond Hamiltonians in the
+// context precision (H0 psi) and in FP64 (the on-device energy contraction).
 int install_gates(fl_ctx* c) {
     const int nb = c->L - 1;
-    int rc0 = drop_dense_plans(c);
-    if (rc0) return rc0;
+    int rc = drop_dense_plans(c);
+    if (rc) return rc;
     std::vector<cd> both((size_t)2 * nb * 16);
     for (int b = 0; b < nb; ++b)
         for (int i = 0; i < 4; ++i)
@@ -202,10 +217,16 @@ int install_gates(fl_ctx* c) {
                 both[(size_t)b * 16 + 4 * i + j] = c->G[(size_t)b * 16 + 4 * i + j];
                 both[(size_t)(nb + b) * 16 + 4 * i + j] = std::conj(c->G[(size_t)b * 16 + 4 * j + i]);
             }
-    int rc = upload_mats(c, c->d_gates, both, (size_t)2 * nb);
+    Staged st;
+    rc = stage_slot(c, &st.buf, &st.slot);
     if (rc) return rc;
-    if (c->have_h) return upload_mats(c, c->d_h, c->h, nb);
-    return FL_OK;
+    const int rb = c->dtype == FL_C64 ? 4 : 8;
+    stage_mats(st, c->d_gates, both, (size_t)2 * nb, rb);
+    if (c->have_h) {
+        stage_mats(st, c->d_h, c->h, nb, rb);
+        stage_mats(st, c->d_h64, c->h, nb, 8);
+    }
+    return stage_commit(c, st);
 }
 
 void read_c16(const double* src, cd* dst) {
@@ -224,22 +245,20 @@ void rho_from16(const double* v, cd* rho) {
         }
 }
 
-int launch_cover_rdm(fl_ctx* c, const void* psi, int* grid_out) {
+// The bond reductions of psi into partials[grid][L][16] (grid <= maxgrid).
+int launch_cover_rdm(fl_ctx* c, const void* psi, double* partials, int maxgrid, int* grid_out) {
     if (c->use_grp) {
-        const int grid = (int)std::min<uint32_t>(ntiles(c->geom_grp), kReduceGrid);
+        const int grid = (int)std::min<uint32_t>(ntiles(c->geom_grp), (uint32_t)maxgrid);
         for (const fl_pass& p : c->cover_grp) {
-            hipError_t e = fl::launch_rdm_groups(c->geom_grp, psi, p, c->d_part, grid, c->L, c->stream);
+            hipError_t e = fl::launch_rdm_groups(c->geom_grp, psi, p, partials, grid, c->L, c->stream);
             if (e != hipSuccess) return fail_hip(e, "k_rdm_groups launch");
         }
         *grid_out = grid;
         return FL_OK;
     }
-    const int grid = (int)std::min<uint32_t>(ntiles(c->geom_rdm), kReduceGrid);
-    for (size_t k = 0; k < c->cover_rdm.size(); ++k) {
-        const fl_win& w = c->cover_win[k];
-        hipError_t e = w.h >= 0 ? fl::launch_rdm_win(c->geom_rdm, psi, w, c->d_part, grid, c->L, c->stream)
-                                : fl::launch_rdm(c->dtype, c->geom_rdm, psi, c->cover_rdm[k], c->d_part, grid, c->L,
-                                                 c->stream);
+    const int grid = (int)std::min<uint32_t>(ntiles(c->geom_rdm), (uint32_t)maxgrid);
+    for (const fl_pass& p : c->cover_rdm) {
+        hipError_t e = fl::launch_rdm(c->dtype, c->geom_rdm, psi, p, partials, grid, c->L, c->stream);
         if (e != hipSuccess) return fail_hip(e, "k_rdm launch");
     }
     *grid_out = grid;
@@ -394,18 +413,21 @@ int upload_tables_and_init(fl_ctx* c, void* psi, const std::vector<cd>& tlo, con
                            const std::vector<cd>& thi, int a, int b) {
     const size_t n = tlo.size() + tmid.size() + thi.size();
     if (n * 2 * sizeof(double) > kStageBytes || n > (size_t)3 * 4096) return fail(FL_EINVAL, "internal: init tables too large");
-    unsigned char* buf = nullptr;
-    int slot = 0;
-    int rc = stage_slot(c, &buf, &slot);
+    Staged st;
+    int rc = stage_slot(c, &st.buf, &st.slot);
     if (rc) return rc;
-    double* t = reinterpret_cast<double*>(buf);
+    double* t = reinterpret_cast<double*>(st.buf);
     size_t k = 0;
     for (const std::vector<cd>* v : {&tlo, &tmid, &thi})
         for (const cd& z : *v) {
             t[k++] = z.real();
             t[k++] = z.imag();
         }
-    rc = stage_upload(c, slot, c->d_tabs, k * sizeof(double));
+    st.dst[0] = c->d_tabs;
+    st.len[0] = k * sizeof(double);
+    st.used = st.len[0];
+    st.n = 1;
+    rc = stage_commit(c, st);
     if (rc) return rc;
     hipError_t e = fl::launch_init(c->dtype, psi, c->L, c->d_tabs, a, b, c->stream);
     if (e != hipSuccess) return fail_hip(e, "k_init launch");
@@ -459,28 +481,12 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
         c->geom_grp = fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64);
         c->cover_grp = fl::plan_cover_groups(c->geom_grp);
     }
-    // complex64 passes whose bonds all lie inside the high window (no low-bit
-    // bond, no norm) run in the register-window reduction kernel
-    for (const fl_pass& p : c->cover_rdm) {
-        fl_win w;
-        w.h = -1;
-        for (int i = 0; i < 8; ++i) w.slot[i] = -1;
-        bool ok = dtype == FL_C64 && c->geom_rdm.W == FL_KMAX_RDM - FL_LOWBITS && c->geom_rdm.C == FL_LOWBITS &&
-                  p.flags == 0 && p.ngroups > 0;
-        for (int gi = 0; ok && gi < p.ngroups; ++gi) {
-            const int i = p.u0[gi] - FL_LOWBITS;
-            if (i < 0 || i + 1 >= c->geom_rdm.W || p.nops[gi] != 1) ok = false;
-            else w.slot[i] = p.ops[gi][0];
-        }
-        if (ok) w.h = p.h;
-        else for (int i = 0; i < 8; ++i) w.slot[i] = -1;
-        c->cover_win.push_back(w);
-    }
     const int nb = L - 1;
     const size_t rb = dtype == FL_C64 ? 4 : 8;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = hipMalloc(&c->d_gates, (size_t)2 * nb * 32 * rb);
     if (e == hipSuccess) e = hipMalloc(&c->d_h, (size_t)nb * 32 * rb);
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_h64, (size_t)nb * 32 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_part, (size_t)kReduceGrid * L * 16 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_red, (size_t)2 * L * 16 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_red, (size_t)2 * L * 16 * sizeof(double), 0);
@@ -509,6 +515,7 @@ int fl_destroy(fl_ctx* c) {
     if (c->h_stage) (void)hipHostFree(c->h_stage);
     if (c->d_gates) (void)hipFree(c->d_gates);
     if (c->d_h) (void)hipFree(c->d_h);
+    if (c->d_h64) (void)hipFree(c->d_h64);
     if (c->d_part) (void)hipFree(c->d_part);
     if (c->d_red) (void)hipFree(c->d_red);
     if (c->h_red) (void)hipHostFree(c->h_red);
@@ -662,7 +669,7 @@ int fl_expect_energy(fl_ctx* c, const void* psi, double out[2], double* rdm) {
     if (!c->have_h) return fail(FL_ESTATE, "no bond Hamiltonians: call fl_set_bonds first");
     const int L = c->L;
     int grid = 0;
-    rc = launch_cover_rdm(c, psi, &grid);
+    rc = launch_cover_rdm(c, psi, c->d_part, kReduceGrid, &grid);
     if (rc) return rc;
     hipError_t e = fl::launch_finalize(c->d_part, grid, L * 16, c->d_red, c->stream);
     if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
@@ -762,7 +769,7 @@ int fl_grad(fl_ctx* c, void* psi_n, void* const* ckpts, int64_t n, int64_t K, co
     const size_t bytes = (size_t)(1ull << L) * amp_bytes(c->dtype);
     // 1. bond density matrices of psi_n (explicit terms) -> d_red[0 .. L*16)
     int grid = 0;
-    rc = launch_cover_rdm(c, psi_n, &grid);
+    rc = launch_cover_rdm(c, psi_n, c->d_part, kReduceGrid, &grid);
     if (rc) return rc;
     hipError_t e = fl::launch_finalize(c->d_part, grid, L * 16, c->d_red, c->stream);
     if (e != hipSuccess) return fail_hip(e, "k_finalize launch");

@@ -72,13 +72,6 @@ static_assert(offsetof(fl_pass, opg) % 4 == 0 && sizeof(((fl_pass*)0)->opg[0]) %
 static_assert(offsetof(fl_pass, ops) % 4 == 0 && sizeof(((fl_pass*)0)->ops[0]) % 4 == 0, "ops rows not word aligned");
 #endif
 
-// A reduction pass over window bonds only: slot[i] is the output slot of the
-// bond on window bits (h + i, h + i + 1), or -1 when the pass skips it.
-struct fl_win {
-    int32_t h;
-    int32_t slot[8];
-};
-
 struct fl_geom {
     int L, C, W, K, R;
 };

@@ -14,9 +14,6 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
 // of geometry (L, 13, 5) (L >= 14)
 hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
                              int nslot, hipStream_t s);
-// complex64 window-bond pass (see k_rdm_win); the geometry must have W = FL_KMAX_RDM - FL_LOWBITS
-hipError_t launch_rdm_win(const fl_geom& g, const void* psi, const fl_win& pw, double* partials, int grid, int nslot,
-                          hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblocks, int nvals, double* out, hipStream_t s);
 hipError_t launch_init(int dtype, void* psi, int L, const void* tabs, int a, int b, hipStream_t s);
 hipError_t launch_overlap(int dta, const void* a, int dtb, const void* b, uint64_t n, double* partials, int grid,

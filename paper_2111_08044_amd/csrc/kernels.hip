@@ -3,9 +3,10 @@
 //  k_sweep_tiles / k_sweep
 //             fused gate sweep: one HBM read + write of the state applies
 //             every gate of a pass (Sec. II Eq. (2), fused as in Sec. II).
-//  k_rdm_groups / k_rdm_tiles / k_rdm_win / k_rdm
+//  k_rdm_groups / k_rdm_tiles / k_rdm
 //             two-site reduced density matrices of the bonds of a pass (plus
-//             the norm), FP64 accumulation (Sec. II Eq. (1); Sec. IV Eq. (10)).
+//             the norm): exact products of the stored amplitudes, FP64 sums
+//             (Sec. II Eq. (1); Sec. IV Eq. (10)).
 //  k_apply_h  lambda = H0 psi, out of place (Sec. IV Eq. (11), Sec. V).
 //  k_adjoint  reverse replay with G^dagger and the overlap terms of the
 //             gradient of <H0>.
@@ -650,21 +651,55 @@ __device__ __forceinline__ void tr_steps_f32(float (&v)[N], int lane) {
     }
 }
 
-template <typename T, int N, int D>
-__device__ __forceinline__ void tr_steps(T (&v)[N], int lane) {
+// FP64 form: the same lane pattern as tr_steps_f32, moving each double as its
+// two 32-bit halves (two permlane swaps or two DPP moves per value); the adds
+// are FP64.
+template <int CTRL>
+__device__ __forceinline__ double fl_dpp_d(double x) {
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+template <int N, int D>
+__device__ __forceinline__ void tr_steps_f64(double (&v)[N], int lane) {
     if constexpr (N > 1) {
         constexpr int H = N / 2;
-        const bool upper = (lane & D) != 0;
 #pragma unroll
         for (int k = 0; k < H; ++k) {
-            const T keep = upper ? v[k + H] : v[k];
-            const T send = upper ? v[k] : v[k + H];
-            v[k] = keep + __shfl_xor(send, D);
+            if constexpr (D == 32 || D == 16) {
+                const uint64_t a = (uint64_t)__double_as_longlong(v[k]), b = (uint64_t)__double_as_longlong(v[k + H]);
+                const auto rl = (D == 32) ? __builtin_amdgcn_permlane32_swap((uint32_t)a, (uint32_t)b, false, false)
+                                          : __builtin_amdgcn_permlane16_swap((uint32_t)a, (uint32_t)b, false, false);
+                const auto rh = (D == 32)
+                                    ? __builtin_amdgcn_permlane32_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false)
+                                    : __builtin_amdgcn_permlane16_swap((uint32_t)(a >> 32), (uint32_t)(b >> 32), false, false);
+                const double x = __longlong_as_double((long long)(((uint64_t)rh[0] << 32) | rl[0]));
+                const double y = __longlong_as_double((long long)(((uint64_t)rh[1] << 32) | rl[1]));
+                v[k] = x + y;
+            } else {
+                const bool upper = (lane & D) != 0;
+                const double keep = upper ? v[k + H] : v[k];
+                const double send = upper ? v[k] : v[k + H];
+                double got;
+                if constexpr (D == 8)
+                    got = fl_dpp_d<0x128>(send);
+                else if constexpr (D == 4)
+                    got = fl_dpp_d<0x141>(send);
+                else
+                    got = __shfl_xor(send, D);
+                v[k] = keep + got;
+            }
         }
-        tr_steps<T, H, D / 2>(*reinterpret_cast<T(*)[H]>(&v[0]), lane);
+        tr_steps_f64<H, D / 2>(*reinterpret_cast<double(*)[H]>(&v[0]), lane);
     } else {
-#pragma unroll
-        for (int d = D; d >= 1; d >>= 1) v[0] += __shfl_xor(v[0], d);
+        if constexpr (D >= 32) v[0] += __shfl_xor(v[0], 32);
+        if constexpr (D >= 16) v[0] += __shfl_xor(v[0], 16);
+        if constexpr (D >= 8) v[0] += fl_dpp_d<0x128>(v[0]);
+        if constexpr (D >= 4) v[0] += fl_dpp_d<0x141>(v[0]);
+        if constexpr (D >= 2) v[0] += fl_dpp_d<0x4E>(v[0]);
+        if constexpr (D >= 1) v[0] += fl_dpp_d<0xB1>(v[0]);
     }
 }
 
@@ -674,7 +709,7 @@ __device__ __forceinline__ T wave_transpose_reduce(T (&v)[NV]) {
     if constexpr (sizeof(T) == 4)
         tr_steps_f32<NV, 32>(v, threadIdx.x & 63);
     else
-        tr_steps<T, NV, 32>(v, threadIdx.x & 63);
+        tr_steps_f64<NV, 32>(v, threadIdx.x & 63);
     return v[0];
 }
 
@@ -789,10 +824,9 @@ __global__ __launch_bounds__(FL_NT) void k_rdm(const typename CT<T>::c* __restri
 }
 
 // Full-size tiles: persistent workgroups with the next tile prefetched into
-// registers (as in k_sweep_tiles).  For complex64 states each lane sums its
-// products over one tile in FP32, the wave reduces those 16 partials in FP32,
-// and lanes then accumulate the per-tile sums in FP64 across tiles; complex128
-// states use FP64 throughout.
+// registers (as in k_sweep_tiles).  All sums are FP64: complex64 amplitudes
+// are widened to FP64, so every product of two of them is exact and only the
+// FP64 additions round; complex128 states use FP64 throughout.
 template <typename T, int KT, int NT>
 __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __restrict__ psi, int W, uint32_t ntiles,
                                                   fl_pass pd, double* __restrict__ partials, int nslot) {
@@ -819,26 +853,25 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
 #pragma unroll
         for (int s = 0; s < ITER; ++s) v[s] = *reinterpret_cast<const v16*>(src + s * tstride);
         __syncthreads();
-        T tn = 0;
 #pragma unroll
         for (int s = 0; s < ITER; ++s) {
             const uint32_t j = APL * (threadIdx.x + s * NT);
             if constexpr (sizeof(T) == 4) {
                 lds[fl_swz(j)] = make_float2(v[s].x, v[s].y);
                 lds[fl_swz(j + 1)] = make_float2(v[s].z, v[s].w);
-                tn = fma(v[s].x, v[s].x, fma(v[s].y, v[s].y, fma(v[s].z, v[s].z, fma(v[s].w, v[s].w, tn))));
+                nrm = fma((double)v[s].x, (double)v[s].x, fma((double)v[s].y, (double)v[s].y, nrm));
+                nrm = fma((double)v[s].z, (double)v[s].z, fma((double)v[s].w, (double)v[s].w, nrm));
             } else {
                 lds[fl_swz(j)] = v[s];
-                tn = fma(v[s].x, v[s].x, fma(v[s].y, v[s].y, tn));
+                nrm = fma(v[s].x, v[s].x, fma(v[s].y, v[s].y, nrm));
             }
         }
-        nrm += (double)tn;
         __syncthreads();
         for (int g = 0; g < pd.ngroups; ++g) {
             const int u = pass_u0(pd, g);
-            T r[16];
+            double r[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) r[k] = 0;
+            for (int k = 0; k < 16; ++k) r[k] = 0.0;
             // slot(spread(tid + NT s) | l << u) = slot(spread(tid)) ^ slot(spread(NT s)) ^ slot(l << u)
             // (the swizzle is linear over XOR; the three parts have disjoint
             // bits), the last two uniform: one VALU XOR per read
@@ -857,18 +890,18 @@ __global__ __launch_bounds__(NT) void k_rdm_tiles(const typename CT<T>::c* __res
             }
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                T ar[4], ai[4];
+                double ar[4], ai[4];
 #pragma unroll
                 for (int l = 0; l < 4; ++l) {
-                    ar[l] = q[s][l].x;
-                    ai[l] = q[s][l].y;
+                    ar[l] = (double)q[s][l].x;
+                    ai[l] = (double)q[s][l].y;
                 }
-                rdm_quad<T>(ar, ai, r);
+                rdm_quad<double>(ar, ai, r);
             }
             // lane l holds the sum of value l >> 2; one lane of each four adds
             // it, the others add zero (an LDS atomic with every lane active)
-            const T red = wave_transpose_reduce<T, 16>(r);
-            __hip_atomic_fetch_add(&wacc[wave][g][lane >> 2], (lane & 3) == 0 ? (double)red : 0.0, __ATOMIC_RELAXED,
+            const double red = wave_transpose_reduce<double, 16>(r);
+            __hip_atomic_fetch_add(&wacc[wave][g][lane >> 2], (lane & 3) == 0 ? red : 0.0, __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
@@ -902,19 +935,19 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 // Density-matrix sums of the bond on register bits (I, I+1) of a register group.
 template <int R, int I>
-__device__ __forceinline__ void group_bond_sums(const float (&vr)[1 << R], const float (&vi)[1 << R], float (&r)[16]) {
+__device__ __forceinline__ void group_bond_sums(const double (&vr)[1 << R], const double (&vi)[1 << R], double (&r)[16]) {
     // (immediate-operand markers keep the bit variants apart, as in apply_pair_g)
     __asm__ volatile("; bond sums on register bits %0" ::"i"(I));
 #pragma unroll
     for (int c = 0; c < (1 << R) / 4; ++c) {
         const int b = (c & ((1 << I) - 1)) | ((c >> I) << (I + 2));
-        float ar[4], ai[4];
+        double ar[4], ai[4];
 #pragma unroll
         for (int l = 0; l < 4; ++l) {
             ar[l] = vr[b | (l << I)];
             ai[l] = vi[b | (l << I)];
         }
-        rdm_quad<float>(ar, ai, r);
+        rdm_quad<double>(ar, ai, r);
     }
     __asm__ volatile("; end bond sums on register bits %0" ::"i"(I));
 }
@@ -924,11 +957,11 @@ __device__ __forceinline__ void group_bond_sums(const float (&vr)[1 << R], const
 // come packed into groups of R consecutive tile bits, every thread reads a
 // group's 2^R amplitudes from LDS once and forms the sums of all the group's
 // bonds from registers (8 quads per bond and thread), so each LDS word is read
-// once per group rather than once per bond.  Per tile, each lane sums its
-// quads in FP32, the wave sums the lanes in FP32 (512 quads), and the result
-// goes into FP64 per-wave LDS accumulators; the norm is summed in FP32 per
-// tile and in FP64 across tiles.  Persistent workgroups; partials as in
-// k_rdm_tiles.
+// once per group rather than once per bond.  The group's amplitudes are
+// widened to FP64 when they leave LDS, so each product of two FP32 values is
+// exact; each lane sums its quads in FP64, the wave tree is FP64 and its
+// result goes into FP64 per-wave LDS accumulators.  The norm is an FP64 sum
+// as well.  Persistent workgroups; partials as in k_rdm_tiles.
 template <int R, int KT, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_rdm_groups(
     const float2* __restrict__ psi, int W, uint32_t ntiles, fl_pass pd, double* __restrict__ partials, int nslot) {
@@ -959,15 +992,19 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
 #pragma unroll
         for (int s = 0; s < ITER; ++s) v[s] = *reinterpret_cast<const float4*>(src + s * tstride);
         __syncthreads();   // the previous tile's LDS reads (and the accumulator reset) are done
-        float tn = 0.f;
 #pragma unroll
         for (int s = 0; s < ITER; ++s) {
             const uint32_t l = l0 + s * (2 * NT);
             lds[l] = make_float2(v[s].x, v[s].y);
             lds[l ^ 1] = make_float2(v[s].z, v[s].w);
-            tn = fmaf(v[s].x, v[s].x, fmaf(v[s].y, v[s].y, fmaf(v[s].z, v[s].z, fmaf(v[s].w, v[s].w, tn))));
         }
-        nrm += (double)tn;
+        if (pd.flags & 1) {
+#pragma unroll
+            for (int s = 0; s < ITER; ++s) {
+                nrm = fma((double)v[s].x, (double)v[s].x, fma((double)v[s].y, (double)v[s].y, nrm));
+                nrm = fma((double)v[s].z, (double)v[s].z, fma((double)v[s].w, (double)v[s].w, nrm));
+            }
+        }
         __syncthreads();
         int row = 0;
         for (int g = 0; g < ng; ++g) {
@@ -981,12 +1018,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             la[0] = sweep_swz<float>(fl_spread(threadIdx.x, u0, R)) * 8u;
 #pragma unroll
             for (int m = 1; m < (1 << R); ++m) la[m] = la[m & (m - 1)] ^ bk[__builtin_ctz(m)];
-            float vr[1 << R], vi[1 << R];
+            double vr[1 << R], vi[1 << R];
 #pragma unroll
             for (int m = 0; m < (1 << R); ++m) {
                 const float2 a = *reinterpret_cast<const float2*>(lb + la[m]);
-                vr[m] = a.x;
-                vi[m] = a.y;
+                vr[m] = (double)a.x;
+                vi[m] = (double)a.y;
             }
             // the group's bonds sit on pair bits i (ops in increasing i): one
             // compile-time code block per pair position, run when present
@@ -995,15 +1032,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             static_for<0, R - 1>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 if ((present >> i) & 1u) {
-                    float r[16];
+                    double r[16];
 #pragma unroll
-                    for (int q = 0; q < 16; ++q) r[q] = 0.f;
+                    for (int q = 0; q < 16; ++q) r[q] = 0.0;
                     group_bond_sums<R, i>(vr, vi, r);
                     // lane l holds the sum of value l >> 2; one lane of each four
                     // adds it, the others add zero (an LDS atomic with every lane active)
-                    const float red = wave_transpose_reduce<float, 16>(r);
+                    const double red = wave_transpose_reduce<double, 16>(r);
                     const int rw = row + __builtin_popcount(present & ((1u << i) - 1u));
-                    __hip_atomic_fetch_add(&wacc[wave][rw][lane >> 2], (lane & 3) == 0 ? (double)red : 0.0,
+                    __hip_atomic_fetch_add(&wacc[wave][rw][lane >> 2], (lane & 3) == 0 ? red : 0.0,
                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             });
@@ -1039,88 +1076,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
 // ---------------------------------------------------------------------------
 // product state, overlap, finalize
 // ---------------------------------------------------------------------------
-
-// Window-bond reduction (complex64): for a cover pass whose bonds all lie in
-// the high window [h, h+WB), one wave takes one tile at a time with its 64
-// lanes on the C low bits (every load instruction reads 512 contiguous bytes)
-// and the 2^WB window amplitudes of each lane in registers, so the density
-// matrices of all WB-1 window bonds come straight from registers: no LDS
-// staging and no barrier.  Each lane sums its quads in FP32 for up to
-// kFlush tiles, then a wave transpose-reduction moves those sums into FP64
-// accumulators (lane l: value l >> 2 of each bond); the four waves of the
-// workgroup are summed at the end into partials[blockIdx][slot][16] for the
-// bonds the pass asks for (slot[i] >= 0 for window bit pair (i, i+1)).
-template <int WB>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_rdm_win(
-    const float2* __restrict__ psi, uint32_t ntiles, fl_win pw, double* __restrict__ partials, int nslot) {
-    constexpr int C = FL_LOWBITS;
-    constexpr int NB = WB - 1;
-    constexpr int M = 1 << WB;
-    constexpr int kFlush = 8;
-    static_assert(C == 6, "one lane per low-bit value");
-    __shared__ double wsum[4][NB][16];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int h = pw.h;
-    float r[NB][16];
-    double acc[NB];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        acc[i] = 0.0;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) r[i][k] = 0.f;
-    }
-    auto flush = [&]() {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            acc[i] += (double)wave_transpose_reduce<float, 16>(r[i]);
-#pragma unroll
-            for (int k = 0; k < 16; ++k) r[i][k] = 0.f;
-        }
-    };
-    const uint32_t step = gridDim.x * 4u;
-    for (uint32_t t0 = blockIdx.x * 4u + (uint32_t)wave; t0 < ntiles; t0 += kFlush * step) {
-        const uint32_t tend = min(ntiles, t0 + kFlush * step);
-        for (uint32_t t = t0; t < tend; t += step) {
-            const float2* src = psi + fl_tile_base(t, C, WB, h) + lane;
-            // hide the stride from loop-invariant code motion: hoisting the 64
-            // offsets m << h out of the tile loop would take 128 SGPRs and spill
-            uint64_t stride = 1ull << h;
-            __asm__ volatile("" : "+s"(stride));
-            float vr[M], vi[M];
-#pragma unroll
-            for (int m = 0; m < M; ++m) {
-                const float2 a = src[m * stride];
-                vr[m] = a.x;
-                vi[m] = a.y;
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i)
-#pragma unroll
-                for (int c = 0; c < M / 4; ++c) {
-                    const int b = (c & ((1 << i) - 1)) | ((c >> i) << (i + 2));
-                    float ar[4], ai[4];
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) {
-                        ar[l] = vr[b | (l << i)];
-                        ai[l] = vi[b | (l << i)];
-                    }
-                    rdm_quad<float>(ar, ai, r[i]);
-                }
-        }
-        flush();
-    }
-    if ((lane & 3) == 0)
-#pragma unroll
-        for (int i = 0; i < NB; ++i) wsum[wave][i][lane >> 2] = acc[i];
-    __syncthreads();
-    for (int t = threadIdx.x; t < NB * 16; t += 256) {
-        const int i = t >> 4, v = t & 15;
-        const int slot = pw.slot[i];
-        if (slot < 0) continue;
-        partials[((size_t)blockIdx.x * nslot + slot) * 16 + v] = wsum[0][i][v] + wsum[1][i][v] + wsum[2][i][v] + wsum[3][i][v];
-    }
-}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(typename CT<T>::c* __restrict__ psi, const double2* __restrict__ tlo,
@@ -1778,13 +1733,6 @@ hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& p
     if (g.K != FL_KMAX_C64 || g.R != FL_SWEEP_R_C64 || g.W == 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rdm_groups<FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(grid), dim3(FL_SWEEP_NT_C64), 0,
                        s, (const float2*)psi, g.W, ntiles_of(g), pd, partials, nslot);
-    return hipGetLastError();
-}
-
-hipError_t launch_rdm_win(const fl_geom& g, const void* psi, const fl_win& pw, double* partials, int grid, int nslot,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_rdm_win<FL_KMAX_RDM - FL_LOWBITS>, dim3(grid), dim3(256), 0, s, (const float2*)psi,
-                       ntiles_of(g), pw, partials, nslot);
     return hipGetLastError();
 }
 

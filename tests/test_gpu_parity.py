@@ -137,10 +137,12 @@ def test_rdm_energy_and_spread_match_oracle(dtype, L):
     vv = psi.cpu().numpy().astype(np.complex128)   # what the GPU actually holds
     E, N, rho = fl.fl_expect_energy(ctx, psi, rdm=True)
     Er, Nr = O.energy(vv, L, hs)
-    # complex128: FP64 throughout.  complex64: products and per-tile partial
-    # sums (<= 2^12 terms, 64-lane trees included) in FP32, FP64 across tiles;
-    # rounding ~ 2^-24 * sqrt(terms) relative to the norm stays below 2e-7.
-    rtol = 1e-13 if dtype == "c128" else 2e-7
+    # Both precisions sum in FP64; complex64 amplitudes are widened first, so
+    # every product is exact and only FP64 additions round.  The sums run as
+    # per-lane chains of at most 64 terms and trees above them (wave, tiles,
+    # workgroups), so the error is below ~100 * 2^-53 times the sum of the
+    # terms' magnitudes, which is at most N for every entry: 1e-12 N holds.
+    rtol = 1e-13 if dtype == "c128" else 1e-12
     assert abs(N - Nr) < rtol * Nr
     assert abs(E - Er) < rtol * Nr * L
     for b in range(L - 1):
