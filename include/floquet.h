@@ -138,6 +138,24 @@ int fl_apply_period(fl_ctx *ctx, void *psi, int64_t n_periods, int dagger);
  * Reductions: FP64 accumulation, deterministic order.  Synchronises. */
 int fl_expect_energy(fl_ctx *ctx, const void *psi, double out[2], double *rdm);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the energy
+ * readout of fl_expect_energy with every result left on the device and no
+ * allocation and no host synchronisation in the call.
+ *   out  device, 2 doubles: out[0] = <psi|H0|psi>, out[1] = <psi|psi>
+ *   rdm  device, NULL or [L-1][4][4] complex doubles (the bond density
+ *        matrices, as fl_expect_energy)
+ * Both are written by kernels on the context stream; the call returns at
+ * once.  The reduction partials live in a static 4 MiB device array (one per
+ * GPU, kept until the process ends, set up by fl_create), sized for at least
+ * 256 reduction workgroups: chains with (257 * 16 L) doubles > 4 MiB are
+ * rejected with FL_EINVAL (no L <= 34 is).  All calls on one GPU share that
+ * array, so calls that overlap on one GPU (two streams, two threads) race;
+ * nothing in it needs clearing, each call writes every value it reads.
+ * Errors: FL_EINVAL (bad psi, out or rdm not 8-byte aligned device memory,
+ * another device current), FL_ESTATE (no bond Hamiltonians), FL_EHIP. */
+int fl_expect_energy_noalloc(fl_ctx *ctx, const void *psi, double *out, double *rdm);
+
 /* Energy spread (Sec. IV, Eq. (11)) of psi: out[0] = <H0>, out[1] = <H0^2>
  * (= ||H0 psi||^2), out[2] = <psi|psi>, all un-normalised FP64.  ws: device
  * workspace of 2^L amplitudes of the context dtype (receives H0 psi).

@@ -24,7 +24,7 @@ from ._native import (FL_C64, FL_C128, FL_PLAIN, FL_DENSE6_FP32, FL_DENSE6_BF16X
 
 __all__ = [
     "fl_create", "fl_destroy", "fl_set_bonds", "fl_set_gates", "fl_init_state", "fl_init_pairs", "fl_apply_period",
-    "fl_expect_energy", "fl_energy_spread", "fl_overlap", "fl_grad_workspace_bytes", "fl_grad",
+    "fl_expect_energy", "fl_expect_energy_noalloc", "fl_energy_spread", "fl_overlap", "fl_grad_workspace_bytes", "fl_grad",
     "fl_last_error", "fl_xyz_bonds", "fl_xyz_generators", "fl_host_gates", "fl_host_gate_derivative",
     "fl_host_ground_states",
     "fl_plan_query", "fl_tile_map", "fl_host_window_matrix", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
@@ -154,6 +154,22 @@ def fl_expect_energy(ctx: Context, psi, rdm: bool = False):
     check(lib().fl_expect_energy(ctx.handle, _state_ptr(ctx, psi), _dp(out),
                                  _dp(r.view(np.float64)) if rdm else None))
     return (out[0], out[1], r) if rdm else (out[0], out[1])
+
+
+def fl_expect_energy_noalloc(ctx: Context, psi, out, rdm=None):
+    """Energy readout into device tensors, no allocation, no host wait:
+    out (2 float64 on the GPU) <- (<H0>, <psi|psi>); rdm (None or (L-1)*32
+    float64 on the GPU) <- the bond density matrices."""
+    torch = _torch()
+    for name, t, n in (("out", out, 2), ("rdm", rdm, (ctx.L - 1) * 32)):
+        if t is None and name == "rdm":
+            continue
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or t.numel() != n \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 GPU tensor of {n} elements")
+    _stream(ctx)
+    check(lib().fl_expect_energy_noalloc(ctx.handle, _state_ptr(ctx, psi), C.c_void_p(out.data_ptr()),
+                                         C.c_void_p(rdm.data_ptr()) if rdm is not None else None))
 
 
 def fl_energy_spread(ctx: Context, psi, ws):

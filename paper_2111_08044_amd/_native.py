@@ -33,6 +33,7 @@ SIGNATURES = {
     "fl_init_pairs": (C.c_int, [vp, vp, dp, dp]),
     "fl_apply_period": (C.c_int, [vp, vp, i64, C.c_int]),
     "fl_expect_energy": (C.c_int, [vp, vp, dp, dp]),
+    "fl_expect_energy_noalloc": (C.c_int, [vp, vp, vp, vp]),
     "fl_energy_spread": (C.c_int, [vp, vp, vp, dp]),
     "fl_overlap": (C.c_int, [vp, vp, C.c_int, vp, C.c_int, dp]),
     "fl_grad_workspace_bytes": (i64, [vp]),

@@ -21,7 +21,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfloquet.so")
 
-SOURCES = ["kernels.hip", "capi.cpp", "host_math.cpp", "planner.cpp"]
+SOURCES = ["kernels.hip", "noalloc.hip", "capi.cpp", "host_math.cpp", "planner.cpp"]
 # measurement probes (csrc/probe.h), a library of their own
 PROBE_SOURCES = ["probe.hip"]
 PROBE_LIB = os.path.join(PKG, "libflprobe.so")

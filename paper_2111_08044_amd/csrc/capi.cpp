@@ -18,6 +18,7 @@
 #include "fl_common.h"
 #include "host_math.h"
 #include "kernels.h"
+#include "noalloc.h"
 #include "planner.h"
 
 using cd = std::complex<double>;
@@ -46,6 +47,7 @@ constexpr int kPlanBlock = 16;        // periods per planned block
 constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
+constexpr int kMinNoallocGrid = 256;  // fewest reduction workgroups fl_expect_energy_noalloc runs
 constexpr int kStageSlots = 8;        // pinned host staging slots for uploads
 constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 complex doubles (init tables)
 
@@ -463,6 +465,8 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     FL_HIP(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(FL_ENODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+    // the static scratch of fl_expect_energy_noalloc: this device's address
+    FL_HIP(fl::scratch_init(dev));
     fl_ctx* c = new fl_ctx();
     c->L = L;
     c->dtype = dtype;
@@ -692,6 +696,39 @@ int fl_expect_energy(fl_ctx* c, const void* psi, double out[2], double* rdm) {
     }
     out[0] = E;
     out[1] = c->h_red[(size_t)(L - 1) * 16];
+    return FL_OK;
+}
+
+int fl_expect_energy_noalloc(fl_ctx* c, const void* psi, double* out, double* rdm) {
+    if (!c) return fail(FL_EINVAL, "ctx is NULL");
+    int rc = check_state(c, psi, "psi");
+    if (rc) return rc;
+    if (!out || ((uintptr_t)out & 7) || !is_device_ptr(out)) return fail(FL_EINVAL, "out must be 8-byte aligned device memory");
+    if (rdm && (((uintptr_t)rdm & 7) || !is_device_ptr(rdm)))
+        return fail(FL_EINVAL, "rdm must be NULL or 8-byte aligned device memory");
+    if (!c->have_h) return fail(FL_ESTATE, "no bond Hamiltonians: call fl_set_bonds first");
+    int dev = -1;
+    FL_HIP(hipGetDevice(&dev));
+    if (dev != c->dev) return fail(FL_EINVAL, "the context's device must be current");
+    double* scr = static_cast<double*>(fl::scratch_ptr(dev));
+    if (!scr) return fail(FL_ESTATE, "static scratch not set up on this device");
+    // scratch: partials [grid][L][16], then the L*16 finalized sums
+    const int L = c->L;
+    const size_t cap = fl::scratch_bytes() / sizeof(double), row = (size_t)L * 16;
+    const size_t fit = cap > row ? (cap - row) / row : 0;
+    if (fit < (size_t)kMinNoallocGrid)
+        return fail(FL_EINVAL, "L = " + std::to_string(L) + " needs " +
+                                   std::to_string((kMinNoallocGrid + 1) * row * sizeof(double)) +
+                                   " bytes of static scratch, more than its " + std::to_string(fl::scratch_bytes()));
+    const int maxgrid = (int)std::min<size_t>(fit, (size_t)kReduceGrid);
+    int grid = 0;
+    rc = launch_cover_rdm(c, psi, scr, maxgrid, &grid);
+    if (rc) return rc;
+    double* fin = scr + (size_t)grid * row;
+    hipError_t e = fl::launch_finalize(scr, grid, (int)row, fin, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+    e = fl::launch_energy_contract(fin, c->d_h64, L, out, rdm, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "k_energy_contract launch");
     return FL_OK;
 }
 

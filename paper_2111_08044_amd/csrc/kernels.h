@@ -15,6 +15,9 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
 hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
                              int nslot, hipStream_t s);
 hipError_t launch_finalize(const double* partials, int nblocks, int nvals, double* out, hipStream_t s);
+// <H0> and the norm from finalized bond sums red[L*16] and FP64 bond terms h64[(L-1)*32]:
+// out[0] = <H0>, out[1] = <psi|psi>; rdm (may be NULL) = [L-1][4][4] complex
+hipError_t launch_energy_contract(const double* red, const double* h64, int L, double* out, double* rdm, hipStream_t s);
 hipError_t launch_init(int dtype, void* psi, int L, const void* tabs, int a, int b, hipStream_t s);
 hipError_t launch_overlap(int dta, const void* a, int dtb, const void* b, uint64_t n, double* partials, int grid,
                           hipStream_t s);

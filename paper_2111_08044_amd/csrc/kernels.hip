@@ -1157,6 +1157,58 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
     if (threadIdx.x == 0) out[v] = red[0];
 }
 
+// <H0> = sum_b Re tr(h_b rho_b) from the finalized bond sums (Sec. IV,
+// Eq. (10)), in FP64 on the device: thread b expands rho_b from its 16 reals
+// and contracts it with h_b (FP64, row-major complex); thread 0 adds the bond
+// terms in bond order.  out[0] = <H0>, out[1] = <psi|psi>; rdm (optional)
+// receives every rho_b as 4x4 complex.  One workgroup of 64 threads, L <= 65.
+__global__ __launch_bounds__(64) void k_energy_contract(const double* __restrict__ red, const double* __restrict__ h64,
+                                                        int L, double* __restrict__ out, double* __restrict__ rdm) {
+    __shared__ double trs[64];
+    const int b = threadIdx.x;
+    if (b < L - 1) {
+        const double* v = red + (size_t)b * 16;
+        double rr[16], ri[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            rr[5 * i] = v[i];
+            ri[5 * i] = 0.0;
+        }
+        int k = 4;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = i + 1; j < 4; ++j) {
+                rr[4 * i + j] = v[k];
+                ri[4 * i + j] = v[k + 1];
+                rr[4 * j + i] = v[k];
+                ri[4 * j + i] = -v[k + 1];
+                k += 2;
+            }
+        const double* hb = h64 + (size_t)b * 32;
+        double tr = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) tr += hb[2 * (4 * i + j)] * rr[4 * j + i] - hb[2 * (4 * i + j) + 1] * ri[4 * j + i];
+        trs[b] = tr;
+        if (rdm) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                rdm[(size_t)b * 32 + 2 * q] = rr[q];
+                rdm[(size_t)b * 32 + 2 * q + 1] = ri[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double E = 0.0;
+        for (int q = 0; q < L - 1; ++q) E += trs[q];
+        out[0] = E;
+        out[1] = red[(size_t)(L - 1) * 16];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // lambda = H0 psi, out of place (the Hamiltonian application of Sec. V)
 // ---------------------------------------------------------------------------
@@ -1733,6 +1785,12 @@ hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& p
     if (g.K != FL_KMAX_C64 || g.R != FL_SWEEP_R_C64 || g.W == 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_rdm_groups<FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(grid), dim3(FL_SWEEP_NT_C64), 0,
                        s, (const float2*)psi, g.W, ntiles_of(g), pd, partials, nslot);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_contract(const double* red, const double* h64, int L, double* out, double* rdm, hipStream_t s) {
+    if (L < 2 || L > 65) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_energy_contract, dim3(1), dim3(64), 0, s, red, h64, L, out, rdm);
     return hipGetLastError();
 }
 
