@@ -78,12 +78,14 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-l34", action="store_true", help="skip the L=34 (128 GiB, in place) leg")
     ap.add_argument("--cpu-sample-gates", type=int, default=3)
-    ap.add_argument("--study", choices=["precision", "echo", "gue", "long", "sizes"], default=None,
+    ap.add_argument("--study", choices=["precision", "echo", "gue", "long", "sizes", "adjoint"], default=None,
                     help="instead of the throughput benchmark: error versus depth of the precision "
                          "variants against an FP64 GPU run (precision), the echo overlap error (echo), "
                          "heating of the paper's GUE circuit versus drive frequency (gue), or the energy "
-                         "density every 100 periods of a long run (long, with --L 34), or time per "
-                         "period and per readout versus L = 16..34 (sizes)")
+                         "density every 100 periods of a long run (long, with --L 34), time per "
+                         "period and per readout versus L = 16..34 (sizes), or only the adjoint/forward "
+                         "ratio at --L (adjoint: one forward and one gradient of 200 periods, K = 50, "
+                         "after one untimed repetition)")
     ap.add_argument("--cpu-baseline-scaling", action="store_true",
                     help="only the cpu_baseline leg, at L = 20..28: the oracle's time per period and its "
                          "a L 2^L fit (no GPU)")
@@ -96,9 +98,14 @@ def parse():
     ap.add_argument("--echo-model", choices=["xyz", "gue"], default="xyz",
                     help="circuit of --study echo: the XYZ+fields chain or the paper's GUE circuit")
     ap.add_argument("--omega", type=float, default=8.0, help="drive frequency of --study echo --echo-model gue")
+    ap.add_argument("--depths", type=str, default=None,
+                    help="comma-separated echo depths t_f of --study echo (default: 1, 2, 5, 10, ... up to "
+                         "--max-periods)")
     ap.add_argument("--sweep-only", type=int, default=0, metavar="N",
                     help="only initialise the state and run N periods of the plain sweep, then exit "
                          "(a short program for hardware counter runs)")
+    ap.add_argument("--sweep-variant", choices=["plain", "dense6_fp32", "dense6_bf16x3", "dense4_fp32"],
+                    default="plain", help="the complex64 variant --sweep-only runs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the state once (a plain device copy of known size, the reference "
                          "for scaling hardware byte counters)")
@@ -329,7 +336,7 @@ def precision_study(fl, torch, L, nmax, variants=("plain", "dense6_fp32", "dense
             "ms_per_period": {k: round(v / t * 1e3, 3) for k, v in times.items()}}
 
 
-def echo_study(fl, torch, L, nmax, model="xyz", omega=8.0):
+def echo_study(fl, torch, L, nmax, model="xyz", omega=8.0, depths=None):
     """Echo of Sec. V: evolve d periods with U_F, then d with U_F^dagger, and
     report |1 - <psi0|psi'0>| and the infidelity, complex64 plain sweep.
     model "xyz": the XYZ+fields chain from a product state; "gue": the paper's
@@ -346,17 +353,20 @@ def echo_study(fl, torch, L, nmax, model="xyz", omega=8.0):
         e.set_xyz(w["J"], w["fields"], w["T"])
         e.init(psi0, w["spinors"])
     rows = []
-    for d in _depths(nmax):
+    chunk = 1000 if L < 32 else 100   # a progress line every ~25 s at L = 34
+    t_start = time.perf_counter()
+    for d in (depths or _depths(nmax)):
         psi.copy_(psi0)
         for dagger in (False, True):
             left = d
             while left > 0:   # chunks, so that a long run reports its progress
-                k = min(left, 1000)
+                k = min(left, chunk)
                 e.step(psi, k, dagger=dagger)
                 left -= k
-                if d > 1000:
+                if d > chunk:
                     torch.cuda.synchronize()
-                    print(json.dumps({"t_f_periods": d, "dagger": dagger, "left": left}), file=sys.stderr, flush=True)
+                    print(json.dumps({"t_f_periods": d, "dagger": dagger, "left": left,
+                                      "elapsed_s": round(time.perf_counter() - t_start, 1)}), file=sys.stderr, flush=True)
         ov, n0, n1 = e.overlap(psi0, psi)
         row = {"t_f_periods": d, "overlap_error": abs(1.0 - ov), "infidelity": 1.0 - abs(ov) ** 2 / (n0 * n1),
                "norm_minus_1": n1 - 1.0}
@@ -548,10 +558,14 @@ def main():
         print(json.dumps(precision_study(fl, torch, L, args.max_periods, args.variants.split(","))), flush=True)
         return
     if args.study == "echo":
-        print(json.dumps(echo_study(fl, torch, L, args.max_periods, args.echo_model, args.omega)), flush=True)
+        depths = [int(x) for x in args.depths.split(",")] if args.depths else None
+        print(json.dumps(echo_study(fl, torch, L, args.max_periods, args.echo_model, args.omega, depths)), flush=True)
         return
     if args.study == "sizes":
         print(json.dumps(size_scaling(fl, torch, list(range(16, 35, 2)))), flush=True)
+        return
+    if args.study == "adjoint":
+        print(json.dumps(adjoint_ratio(fl, torch, L=L)), flush=True)
         return
     if args.study == "long":
         print(json.dumps(long_run(fl, torch, L, args.max_periods)), flush=True)
@@ -561,15 +575,16 @@ def main():
         print(json.dumps(gue_study(fl, torch, L, omegas, args.tmax)), flush=True)
         return
     w = fin.xyz_workload(L)
-    eng = fl.FloquetEngine(L, "c64")
+    eng = fl.FloquetEngine(L, "c64", args.sweep_variant if args.sweep_only > 0 else "plain")
     eng.set_xyz(w["J"], w["fields"], w["T"])
     psi = eng.new_state()
     eng.init(psi, w["spinors"])
     if args.sweep_only > 0:
         eng.step(psi, args.sweep_only)
         torch.cuda.synchronize()
-        print(json.dumps({"sweep_only": args.sweep_only, "L": L, "sweep_launches": plan_passes(fl, L, args.sweep_only)}),
-              flush=True)
+        kind = {"plain": 0, "dense6_fp32": 4, "dense6_bf16x3": 4, "dense4_fp32": 5}[args.sweep_variant]
+        print(json.dumps({"sweep_only": args.sweep_only, "L": L, "variant": args.sweep_variant,
+                          "launches": int(fl.fl_plan_query(L, "c64", kind, args.sweep_only, False)[3])}), flush=True)
         return
     if args.calibrate_copy:
         tmp = torch.empty_like(psi)

@@ -46,6 +46,9 @@
 #ifndef FL_RDM_GROUPS
 #define FL_RDM_GROUPS 1      // complex64 reductions on 13-bit tiles with register groups (L >= 14)
 #endif
+#ifndef FL_DENSE4_NW
+#define FL_DENSE4_NW 4       // waves per workgroup of the 4-qubit-window MFMA kernel
+#endif
 #ifndef FL_DIRECT_MIN_U0
 #define FL_DIRECT_MIN_U0 4   // lowest group bit for direct HBM <-> register transfers
 #endif

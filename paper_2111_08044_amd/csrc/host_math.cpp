@@ -200,11 +200,14 @@ void window_matrix(const cd* const* gates, const int* pos, int nops, cd* U) {
 }
 
 void window_fragments4(const cd* U, float* out) {
-    // real form A[2m'+c'][2m+c] of the 16x16 complex U; lane l, step s holds
-    // A[l % 32][2 s + l / 32]
+    // real form A[2m'+c'][2m+c] of the 16x16 complex U with its columns taken
+    // component-major, k' = 16 c + m: lane l, step s holds A[l % 32][k] for
+    // k' = 2 s + l / 32, i.e. m = k' mod 16, c = k' / 16, so that steps s and
+    // s + 8 take the real and imaginary part of one amplitude
     for (int l = 0; l < 64; ++l)
         for (int st = 0; st < 16; ++st) {
-            const int r = l & 31, k = 2 * st + (l >> 5);
+            const int r = l & 31, kc = 2 * st + (l >> 5);
+            const int k = 2 * (kc & 15) + (kc >> 4);
             const cd u = U[(r >> 1) * 16 + (k >> 1)];
             double a;
             if ((r & 1) == 0) a = (k & 1) == 0 ? u.real() : -u.imag();

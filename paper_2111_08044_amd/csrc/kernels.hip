@@ -206,28 +206,28 @@ __device__ __forceinline__ void apply_op(T (&vr)[1 << R], T (&vi)[1 << R], int i
 // tile load / store (global <-> LDS), 16-byte global accesses
 // ---------------------------------------------------------------------------
 
-template <typename T, int KT>
+template <typename T, int KT, int NT = FL_NT>
 __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C,
                                           int h, typename CT<T>::c* lds) {
     typedef typename CT<T>::c cplx;
     if constexpr (sizeof(T) == 4) {
         const int n2 = 1 << (K - 1);  // pairs of amplitudes
         if constexpr (KT > 0) {
-            constexpr int ITER = (1 << (KT - 1)) / FL_NT;
+            constexpr int ITER = (1 << (KT - 1)) / NT;
             float4 v[ITER];
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
-                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                const uint32_t j = 2u * (threadIdx.x + s * NT);
                 v[s] = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
             }
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
-                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                const uint32_t j = 2u * (threadIdx.x + s * NT);
                 lds[fl_swz(j)] = make_float2(v[s].x, v[s].y);
                 lds[fl_swz(j + 1)] = make_float2(v[s].z, v[s].w);
             }
         } else {
-            for (int p = threadIdx.x; p < n2; p += FL_NT) {
+            for (int p = threadIdx.x; p < n2; p += NT) {
                 const uint32_t j = 2u * p;
                 const float4 v = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
                 lds[fl_swz(j)] = make_float2(v.x, v.y);
@@ -237,36 +237,36 @@ __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ 
     } else {
         const int n = 1 << K;
         if constexpr (KT > 0) {
-            constexpr int ITER = (1 << KT) / FL_NT;
+            constexpr int ITER = (1 << KT) / NT;
             cplx v[ITER];
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
-                const uint32_t j = threadIdx.x + s * FL_NT;
+                const uint32_t j = threadIdx.x + s * NT;
                 v[s] = psi[base + fl_tile_offset(j, C, h)];
             }
 #pragma unroll
-            for (int s = 0; s < ITER; ++s) lds[fl_swz(threadIdx.x + s * FL_NT)] = v[s];
+            for (int s = 0; s < ITER; ++s) lds[fl_swz(threadIdx.x + s * NT)] = v[s];
         } else {
-            for (int j = threadIdx.x; j < n; j += FL_NT) lds[fl_swz(j)] = psi[base + fl_tile_offset(j, C, h)];
+            for (int j = threadIdx.x; j < n; j += NT) lds[fl_swz(j)] = psi[base + fl_tile_offset(j, C, h)];
         }
     }
 }
 
-template <typename T, int KT>
+template <typename T, int KT, int NT = FL_NT>
 __device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C, int h,
                                            const typename CT<T>::c* lds) {
     if constexpr (sizeof(T) == 4) {
         const int n2 = 1 << (K - 1);
         if constexpr (KT > 0) {
-            constexpr int ITER = (1 << (KT - 1)) / FL_NT;
+            constexpr int ITER = (1 << (KT - 1)) / NT;
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
-                const uint32_t j = 2u * (threadIdx.x + s * FL_NT);
+                const uint32_t j = 2u * (threadIdx.x + s * NT);
                 const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
                 *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
             }
         } else {
-            for (int p = threadIdx.x; p < n2; p += FL_NT) {
+            for (int p = threadIdx.x; p < n2; p += NT) {
                 const uint32_t j = 2u * p;
                 const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
                 *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
@@ -274,7 +274,7 @@ __device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, 
         }
     } else {
         const int n = 1 << K;
-        for (int j = threadIdx.x; j < n; j += FL_NT) psi[base + fl_tile_offset(j, C, h)] = lds[fl_swz(j)];
+        for (int j = threadIdx.x; j < n; j += NT) psi[base + fl_tile_offset(j, C, h)] = lds[fl_swz(j)];
     }
 }
 
@@ -1330,26 +1330,26 @@ __device__ __forceinline__ void adj_op(T (&pr)[1 << R], T (&pi)[1 << R], T (&lr)
     apply_pair_g<T, R, I>(lr, li, g);
 }
 
-template <typename T, int R, int KT, int KMAX>
-__global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) void k_adjoint(typename CT<T>::c* __restrict__ psi,
+template <typename T, int R, int KT, int KMAX, int NT = FL_NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && NT == FL_NT ? 2 : 1))) void k_adjoint(typename CT<T>::c* __restrict__ psi,
                                                    typename CT<T>::c* __restrict__ lam, const T* __restrict__ gates,
                                                    int C, int W, uint32_t ntiles, fl_pass pd,
                                                    double* __restrict__ Mpart, int nbonds) {
     typedef typename CT<T>::c cplx;
     __shared__ cplx lp[1 << KMAX];
     __shared__ cplx ll[1 << KMAX];
-    __shared__ double wacc[FL_NT / 64][FL_MAX_SLOTS][16];
+    __shared__ double wacc[NT / 64][FL_MAX_SLOTS][16];
     const int K = KT > 0 ? KT : C + W;
     const int h = pd.h;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int t = threadIdx.x; t < (FL_NT / 64) * FL_MAX_SLOTS * 16; t += FL_NT) (&wacc[0][0][0])[t] = 0.0;
-    const uint32_t nsub = 1u << (K - R);   // <= FL_NT for K <= 12, R = 4
+    for (int t = threadIdx.x; t < (NT / 64) * FL_MAX_SLOTS * 16; t += NT) (&wacc[0][0][0])[t] = 0.0;
+    const uint32_t nsub = 1u << (K - R);   // <= NT
     const bool active = threadIdx.x < nsub;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t base = fl_tile_base(tile, C, W, h);
         __syncthreads();
-        tile_load<T, KT>(psi, base, K, C, h, lp);
-        tile_load<T, KT>(lam, base, K, C, h, ll);
+        tile_load<T, KT, NT>(psi, base, K, C, h, lp);
+        tile_load<T, KT, NT>(lam, base, K, C, h, ll);
         __syncthreads();
         for (int g = 0; g < pd.ngroups; ++g) {
             const int u0 = pass_u0(pd, g);
@@ -1424,15 +1424,15 @@ __global__ __launch_bounds__(FL_NT) __attribute__((amdgpu_waves_per_eu(sizeof(T)
             }
             __syncthreads();
         }
-        tile_store<T, KT>(psi, base, K, C, h, lp);
-        tile_store<T, KT>(lam, base, K, C, h, ll);
+        tile_store<T, KT, NT>(psi, base, K, C, h, lp);
+        tile_store<T, KT, NT>(lam, base, K, C, h, ll);
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < pd.nslots * 16; t += FL_NT) {
+    for (int t = threadIdx.x; t < pd.nslots * 16; t += NT) {
         const int sl = t >> 4, v = t & 15;
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < FL_NT / 64; ++w) s += wacc[w][sl][v];
+        for (int w = 0; w < NT / 64; ++w) s += wacc[w][sl][v];
         double* dst = Mpart + ((size_t)blockIdx.x * nbonds + pd.sbond[sl]) * 16 + v;
         *dst += s;
     }
@@ -1481,22 +1481,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lc = lane & 31, lk = lane >> 5;
     const int ncb = FULL ? 4 : 1 << (K - 6 - 5);   // 32-column blocks (1, 2 or 4)
+    const int ng = pd.ngroups;
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
     tile_load<float, 0>(psi, base, K, C, h, lds);
     __syncthreads();
-    for (int g = 0; g < pd.ngroups; ++g) {
-        const int u0 = pass_u0(pd, g);
-        // 4096 float4 (64 KiB) per window; MODE 1 keeps hi at [0, 2048), lo at [2048, 4096)
-        const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 4096 + (size_t)(w * 64 + lane) * (MODE == 0 ? 16 : 8);
-        uint32_t cbase[4];
+    // write Y (registers of one window) back to the FP32 tile: register r of
+    // block cb holds row 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column
+    // 32 cb + lc; slot(cbase | m << u0) = slot(cbase) ^ slot(m << u0), the
+    // second part uniform
+    auto store_fp32 = [&](const fl_f32x16 (&acc)[4], const uint32_t (&cbase)[4], int u0) {
+        const uint32_t mrow = 16 * w + 2 * lk;   // m of register 0 (rows 32w + 4lk, +1)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            if (cb < ncb) {
+                const uint32_t vb = fl_swz(cbase[cb]) * 8u;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const uint32_t m = mrow + 4 * q + p;   // rows 32w + 8q + 4lk + 2p, +1
+                        float2 v;
+                        v.x = acc[cb][4 * q + 2 * p];
+                        v.y = acc[cb][4 * q + 2 * p + 1];
+                        *reinterpret_cast<float2*>(smem + (vb ^ (fl_swz(m << u0) * 8u))) = v;
+                    }
+                }
+            }
+        }
+    };
+    auto column_bases = [&](int u0, uint32_t (&cbase)[4]) {
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) cbase[cb] = fl_spread((32 * cb + lc) & ((1 << (K - 6)) - 1), u0, 6);
-        fl_f32x16 acc[4];
+    };
+    if constexpr (MODE == 0) {
+        for (int g = 0; g < ng; ++g) {
+            const int u0 = pass_u0(pd, g);
+            // 4096 float4 (64 KiB) per window
+            const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 4096 + (size_t)(w * 64 + lane) * 16;
+            uint32_t cbase[4];
+            column_bases(u0, cbase);
+            fl_f32x16 acc[4];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
-        if constexpr (MODE == 0) {
+                for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
             float a[64];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
@@ -1532,10 +1560,40 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[kk], bq[kk % (PF + 1)][cb], acc[cb], 0, 0, 0);
             }
             __syncthreads();
-        } else {
-            // split the tile once into hi / lo planes laid out [column][k]
-            // (every thread reads its amplitudes, the workgroup syncs, then
-            // the planes overwrite the FP32 tile in LDS)
+            store_fp32(acc, cbase, u0);
+            __syncthreads();
+        }
+    } else {
+        // The B operand of a window lives in LDS as two bf16 planes (hi, lo)
+        // laid out [column][k]; element j of the tile (window bits from u) sits
+        // at plane offset o_u(j) = col_u(j) STRIDE + 2 m_u(j) (+1 for the
+        // imaginary part).  col_u and m_u are bit fields of j, so o_u is
+        // additive over indices with disjoint bits.  The planes of the first
+        // window come from the FP32 tile; those of every later window straight
+        // from the previous window's accumulators (split once, when written),
+        // and only the last window writes FP32 again, for the store.
+        __bf16* ph = reinterpret_cast<__bf16*>(smem);
+        __bf16* pl = ph + 128 * FL_DENSE_PLANE_STRIDE;
+        typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+        auto plane_off = [](uint32_t j, int u) {
+            const uint32_t m = (j >> u) & 63;
+            const uint32_t col = (j & ((1u << u) - 1)) | ((j >> (u + 6)) << u);
+            return col * FL_DENSE_PLANE_STRIDE + 2 * m;
+        };
+        // (re, im) of one amplitude are adjacent in a plane: one 32-bit LDS
+        // store per plane; hi = RNE_bf16(x), lo = RNE_bf16(x - hi)
+        auto split_store = [&](float re, float im, uint32_t o) {
+            bf2 hv, lv;
+            hv.x = (__bf16)re;
+            hv.y = (__bf16)im;
+            lv.x = (__bf16)(re - (float)hv.x);
+            lv.y = (__bf16)(im - (float)hv.y);
+            *reinterpret_cast<bf2*>(ph + o) = hv;
+            *reinterpret_cast<bf2*>(pl + o) = lv;
+        };
+        if (ng > 0) {
+            // first window: every thread reads its amplitudes of the FP32
+            // tile, the workgroup syncs, then the planes overwrite the tile
             constexpr int PER = (1 << KMAXD) / 256;
             float2 mine[PER];
             const int nper = FULL ? PER : (1 << K) / 256;
@@ -1544,46 +1602,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             for (int t = 0; t < PER; ++t)
                 if (t < nper) mine[t] = lds[l0 + 256 * t];
             __syncthreads();
-            __bf16* ph = reinterpret_cast<__bf16*>(smem);
-            __bf16* pl = ph + 128 * FL_DENSE_PLANE_STRIDE;
-            // plane offset o(j) = col(j) * STRIDE + 2 m(j) of element j: col and m
-            // are bit fields of j, so o(tid | t << 8) = o(tid) + o(t << 8), the
-            // second term uniform
-            auto plane_off = [&](uint32_t j) {
-                const uint32_t m = (j >> u0) & 63;
-                const uint32_t col = (j & ((1u << u0) - 1)) | ((j >> (u0 + 6)) << u0);
-                return col * FL_DENSE_PLANE_STRIDE + 2 * m;
-            };
-            const uint32_t otid = plane_off(threadIdx.x);
+            const int u0 = pass_u0(pd, 0);
+            const uint32_t otid = plane_off(threadIdx.x, u0);
 #pragma unroll
-            for (int t = 0; t < PER; ++t) {
-                if (t < nper) {
-                    const float2 x = mine[t];
-                    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
-                    bf2 hv, lv;
-                    hv.x = (__bf16)x.x;
-                    hv.y = (__bf16)x.y;
-                    lv.x = (__bf16)(x.x - (float)hv.x);
-                    lv.y = (__bf16)(x.y - (float)hv.y);
-                    // (re, im) of one amplitude are adjacent in a plane: one
-                    // 32-bit LDS store per plane
-                    // readfirstlane: keep the uniform term a scalar (otherwise the
-                    // two products get refactored into one vector multiply)
-                    const uint32_t o = otid + __builtin_amdgcn_readfirstlane(plane_off(256u * (uint32_t)t));
-                    *reinterpret_cast<bf2*>(ph + o) = hv;
-                    *reinterpret_cast<bf2*>(pl + o) = lv;
-                }
-            }
-            // A fragments are loaded after the split so that the two never
-            // occupy registers at the same time
-            fl_bf16x8 ah[8], al[8];
+            for (int t = 0; t < PER; ++t)
+                if (t < nper)
+                    // readfirstlane: keep the uniform term a scalar
+                    split_store(mine[t].x, mine[t].y,
+                                otid + __builtin_amdgcn_readfirstlane(plane_off(256u * (uint32_t)t, u0)));
+            __syncthreads();
+        }
+        // A fragments of a window: 8 steps x 8 bf16 for hi, then for lo
+        fl_bf16x8 ah[8], al[8];
+        auto load_a = [&](int g) {
+            const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 4096 + (size_t)(w * 64 + lane) * 8;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const float4 th = M[q], tl = M[2048 + q];
                 ah[q] = *reinterpret_cast<const fl_bf16x8*>(&th);
                 al[q] = *reinterpret_cast<const fl_bf16x8*>(&tl);
             }
-            __syncthreads();
+        };
+        if (ng > 0) load_a(0);
+        for (int g = 0; g < ng; ++g) {
+            const int u0 = pass_u0(pd, g);
+            uint32_t cbase[4];
+            column_bases(u0, cbase);
+            fl_f32x16 acc[4];
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
 #pragma unroll
             for (int st = 0; st < 8; ++st) {
                 const int k0 = 16 * st + 8 * lk;
@@ -1600,30 +1649,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     }
                 }
             }
-            __syncthreads();
-        }
-        // write Y back to the FP32 tile: register r of block cb holds row
-        // 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column 32 cb + lc
-        // (slots as above: slot(cbase) ^ slot(m << u0), the second part uniform)
-        const uint32_t mrow = 16 * w + 2 * lk;   // m of register 0 (rows 32w + 4lk, +1)
+            // the next window's fragments go into the registers just freed,
+            // so that their latency overlaps the barrier and the split
+            if (g + 1 < ng) load_a(g + 1);
+            __syncthreads();   // every wave has read this window's planes
+            if (g + 1 < ng) {
+                // element of register (cb, q, p): j = cbase[cb] | (mrow + 4q + p) << u0,
+                // three parts with disjoint bits: o(j) = o(cbase | mrow << u0) + o((4q + p) << u0)
+                const int un = pass_u0(pd, g + 1);
+                const uint32_t mrow = 16 * w + 2 * lk;
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) {
-            if (cb < ncb) {
-                const uint32_t vb = fl_swz(cbase[cb]) * 8u;
+                for (int cb = 0; cb < 4; ++cb) {
+                    if (cb < ncb) {
+                        const uint32_t ob = plane_off(cbase[cb] | (mrow << u0), un);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                        for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const uint32_t m = mrow + 4 * q + p;   // rows 32w + 8q + 4lk + 2p, +1
-                        float2 v;
-                        v.x = acc[cb][4 * q + 2 * p];
-                        v.y = acc[cb][4 * q + 2 * p + 1];
-                        *reinterpret_cast<float2*>(smem + (vb ^ (fl_swz(m << u0) * 8u))) = v;
+                            for (int p = 0; p < 2; ++p)
+                                split_store(acc[cb][4 * q + 2 * p], acc[cb][4 * q + 2 * p + 1],
+                                            ob + __builtin_amdgcn_readfirstlane(
+                                                     plane_off((uint32_t)(4 * q + p) << u0, un)));
                     }
                 }
+            } else {
+                store_fp32(acc, cbase, u0);
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
     tile_store<float, 0>(psi, base, K, C, h, lds);
 }
@@ -1637,23 +1689,30 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // A[2m'+c'][2m+c] = (Re U, -Im U; Im U, Re U)[c'][c] at (m', m): exactly one
 // v_mfma_f32_32x32x2f32 output tile, K = 32 in 16 steps of 2.  Column v of X
 // is the 16-vector of amplitudes sharing the other 9 tile bits; a tile has
-// 512 columns, 128 per wave (4 blocks of 32).  Lane l supplies
-// A[l%32][2s + l/32] (16 VGPRs, the same for every wave) and, per block,
-// X[2s + l/32][32 cb + l%32] = the re (l < 32) or im (l >= 32) part of
-// amplitude s of that column.  A wave reads and writes only its own columns,
-// so each window needs one barrier (before the next window's reads).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense4(float2* __restrict__ psi,
-                                                                                      const float4* __restrict__ mats,
-                                                                                      int W, fl_pass pd) {
+// 512 columns, 512 / NW per wave (blocks of 32).  The contraction index runs
+// component-major, k' = 16 c + m: step s takes k' = 2s + l/32, so lane l
+// supplies A[l%32][k'] (16 VGPRs, the same for every wave) and, per block,
+// component s/8 of amplitude 2(s mod 8) + l/32 of its column; steps s and
+// s + 8 use the two halves of one 8-byte LDS read.  A wave reads and writes
+// only its own columns: the columns of wave w are those whose log2(NW)
+// highest bits outside the window equal w, so consecutive windows that leave
+// the same tile bits to the wave index (with NW = 8 all windows below bit 7
+// leave bits 10, 11 and 12) need no barrier between them, only this wave's
+// own LDS order.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_dense4(
+    float2* __restrict__ psi, const float4* __restrict__ mats, int W, fl_pass pd) {
     constexpr int K = 13;
     constexpr int C = FL_LOWBITS;
+    constexpr int NB = 16 / NW;                  // 32-column blocks per wave (512 columns per tile)
+    constexpr int WB = __builtin_ctz(NW);        // column bits that name the wave
     __shared__ __attribute__((aligned(16))) float2 lds[1 << K];
     const char* const lbytes = reinterpret_cast<const char*>(lds);
     const int h = pd.h;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int lc = lane & 31, lk = lane >> 5;
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
-    tile_load<float, K>(psi, base, K, C, h, lds);
+    tile_load<float, K, 64 * NW>(psi, base, K, C, h, lds);
     __syncthreads();
     // A fragments of a window: 64 lanes x 16 floats (4 KiB).  The next
     // window's fragments are fetched while the current window is applied; the
@@ -1678,30 +1737,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         __builtin_amdgcn_sched_barrier(0);
         // slot(spread(col) | s << u0) = slot(spread(col)) ^ slot(s << u0): the
         // second part is uniform (the swizzle is linear over XOR)
-        uint32_t vb[4];
+        uint32_t vb[NB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
-            vb[cb] = fl_swz(fl_spread((uint32_t)(128 * w + 32 * cb + lc), u0, 4)) * 8u;
-        fl_f32x16 acc[4];
+        for (int cb = 0; cb < NB; ++cb)
+            vb[cb] = fl_swz(fl_spread((uint32_t)(32 * NB * w + 32 * cb + lc), u0, 4)) * 8u;
+        fl_f32x16 acc[NB];
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
-        float bq[16][4];
+        float bq[16][NB];
+        // amplitude 2t + lk of the column: slot(spread(col)) ^ slot(lk << u0) ^ slot(2t << u0)
+        const uint32_t lkoff = fl_swz((uint32_t)lk << u0) * 8u;
 #pragma unroll
-        for (int st = 0; st < 16; ++st) {
-            const uint32_t ss = fl_swz((uint32_t)st << u0) * 8u + 4u * (uint32_t)lk;
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t ss = fl_swz((uint32_t)(2 * t) << u0) * 8u;
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) bq[st][cb] = *reinterpret_cast<const float*>(lbytes + ((vb[cb] ^ ss)));
+            for (int cb = 0; cb < NB; ++cb) {
+                const float2 x = *reinterpret_cast<const float2*>(lbytes + ((vb[cb] ^ lkoff) ^ ss));
+                bq[t][cb] = x.x;
+                bq[t + 8][cb] = x.y;
+            }
         }
 #pragma unroll
         for (int st = 0; st < 16; ++st)
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
+            for (int cb = 0; cb < NB; ++cb)
                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], bq[st][cb], acc[cb], 0, 0, 0);
         // register r of block cb holds row 8(r/4) + 4 lk + r%4 = 2m' + c'
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb)
+        for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -1712,11 +1777,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     v.y = acc[cb][4 * q + 2 * p + 1];
                     *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + (vb[cb] ^ (fl_swz(m << u0) * 8u))) = v;
                 }
-        __syncthreads();
+        // the WB tile bits that select a wave's columns: column bits 9 - WB .. 8,
+        // which sit 4 higher when at or above the window, so the set depends
+        // only on how many of them lie below u0
+        auto part = [](int u) { return u <= 9 - WB ? 0 : u - (9 - WB); };
+        if (g + 1 == pd.ngroups || part(pass_u0(pd, g + 1)) != part(u0))
+            __syncthreads();
+        else
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
         for (int k = 0; k < 16; ++k) a[k] = an[k];
     }
-    tile_store<float, K>(psi, base, K, C, h, lds);
+    tile_store<float, K, 64 * NW>(psi, base, K, C, h, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1910,11 +1982,13 @@ hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl
         // [0, 6) plus the window [6, 13), the kernel's fixed geometry
         fl_pass p = pd;
         p.h = FL_LOWBITS;
-        hipLaunchKernelGGL(k_dense4, dim3(1), dim3(256), 0, s, (float2*)psi, (const float4*)mats, 13 - FL_LOWBITS, p);
+        hipLaunchKernelGGL(k_dense4<FL_DENSE4_NW>, dim3(1), dim3(64 * FL_DENSE4_NW), 0, s, (float2*)psi,
+                           (const float4*)mats, 13 - FL_LOWBITS, p);
         return hipGetLastError();
     }
     if (g.C != FL_LOWBITS) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_dense4, dim3(ntiles_of(g)), dim3(256), 0, s, (float2*)psi, (const float4*)mats, g.W, pd);
+    hipLaunchKernelGGL(k_dense4<FL_DENSE4_NW>, dim3(ntiles_of(g)), dim3(64 * FL_DENSE4_NW), 0, s, (float2*)psi,
+                       (const float4*)mats, g.W, pd);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ def test_help_lists_the_studies():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 0
-    for word in ("precision", "echo", "gue", "long", "sizes", "--cpu-baseline-scaling", "--sweep-only"):
+    for word in ("precision", "echo", "gue", "long", "sizes", "adjoint", "--depths", "--sweep-variant",
+                 "--cpu-baseline-scaling", "--sweep-only"):
         assert word in r.stdout
 
 

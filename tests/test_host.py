@@ -372,7 +372,8 @@ def _real_form32(U):
 
 def test_window4_matrix_and_fragments():
     """4-bit windows: U is the product of the embedded gates (a 4-site chain,
-    window bit i = site 3 - i) and lane l, step s holds A[l % 32][2 s + l / 32]."""
+    window bit i = site 3 - i) and lane l, step s holds A[l % 32][2 m + c] for
+    m = k' mod 16, c = k' / 16, k' = 2 s + l / 32 (columns component-major)."""
     rng = np.random.default_rng(8)
     G = np.array([np.linalg.qr(rng.standard_normal((4, 4)) + 1j * rng.standard_normal((4, 4)))[0]
                   for _ in range(5)])
@@ -385,7 +386,8 @@ def test_window4_matrix_and_fragments():
     A = _real_form32(U)
     f = frag.view(np.float32).reshape(64, 16).astype(np.float64)
     l, st = np.meshgrid(np.arange(64), np.arange(16), indexing="ij")
-    assert np.array_equal(f, A[l & 31, 2 * st + (l >> 5)].astype(np.float32).astype(np.float64))
+    kc = 2 * st + (l >> 5)
+    assert np.array_equal(f, A[l & 31, 2 * (kc & 15) + (kc >> 4)].astype(np.float32).astype(np.float64))
     with pytest.raises(fl.FloquetError):
         fl.fl_host_window_matrix(G, [0, 3], 2)   # gate position outside a 4-bit window
 
