@@ -105,7 +105,7 @@ def parse():
                     help="only initialise the state and run N periods of the plain sweep, then exit "
                          "(a short program for hardware counter runs)")
     ap.add_argument("--sweep-variant", choices=["plain", "dense6_fp32", "dense6_bf16x3", "dense4_fp32"],
-                    default="plain", help="the complex64 variant --sweep-only runs")
+                    default="plain", help="the complex64 variant --sweep-only and --study adjoint run")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also copy the state once (a plain device copy of known size, the reference "
                          "for scaling hardware byte counters)")
@@ -247,10 +247,10 @@ def cpu_baseline_scaling(Ls, nrep=2):
             "host": cpu_model(), "host_cpus": os.cpu_count()}
 
 
-def adjoint_ratio(fl, torch, L=24, n=200, K=50):
+def adjoint_ratio(fl, torch, L=24, n=200, K=50, variant="plain"):
     import floquet_inputs as fin
     w = fin.xyz_workload(L)
-    eng = fl.FloquetEngine(L, "c64")
+    eng = fl.FloquetEngine(L, "c64", variant)
     eng.set_xyz(w["J"], w["fields"], w["T"])
     psi = eng.new_state()
     gens = fl.fl_xyz_generators(L)
@@ -270,7 +270,8 @@ def adjoint_ratio(fl, torch, L=24, n=200, K=50):
         g = fl.fl_grad(eng.ctx, psi, ck, n, K, gens, lam)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        res = {"L": L, "n_periods": n, "ckpt_every": K, "forward_s": t1 - t0, "backward_s": t2 - t1,
+        res = {"L": L, "variant": variant, "n_periods": n, "ckpt_every": K, "forward_s": t1 - t0,
+               "backward_s": t2 - t1,
                "ratio_backward_over_forward": (t2 - t1) / (t1 - t0),
                "ratio_total_over_forward": (t2 - t0) / (t1 - t0), "dE_dT": float(g[-1])}
     return res
@@ -565,7 +566,7 @@ def main():
         print(json.dumps(size_scaling(fl, torch, list(range(16, 35, 2)))), flush=True)
         return
     if args.study == "adjoint":
-        print(json.dumps(adjoint_ratio(fl, torch, L=L)), flush=True)
+        print(json.dumps(adjoint_ratio(fl, torch, L=L, variant=args.sweep_variant)), flush=True)
         return
     if args.study == "long":
         print(json.dumps(long_run(fl, torch, L, args.max_periods)), flush=True)
@@ -695,6 +696,9 @@ def main():
         out["adjoint"] = adjoint_ratio(fl, torch)
         # the same ratio at L = 28 (2 GiB states; state, lambda and checkpoints far exceed the caches)
         out["adjoint_L28"] = adjoint_ratio(fl, torch, L=28)
+        # the 4-qubit-window form: MFMA windows forward, their exact adjoints
+        # replayed on the matrix cores
+        out["adjoint_dense4"] = adjoint_ratio(fl, torch, variant="dense4_fp32")
         torch.cuda.empty_cache()
     if not args.no_l34:
         out["l34"] = l34_leg(fl, torch)

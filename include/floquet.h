@@ -185,6 +185,15 @@ int64_t fl_grad_workspace_bytes(const fl_ctx *ctx);
  *   lambda_ws device workspace of fl_grad_workspace_bytes()
  *   grad      host out, (L-1)*P + 1 doubles: d E_n / d theta_{b,p} at
  *             b*P + p, and d E_n / d T last.
+ * The replay undoes the forward exactly up to arithmetic rounding when it
+ * applies the adjoints of the very matrices the forward applied, so that a
+ * reset from a checkpoint meets the state the replay reached.  The plain form
+ * replays the FP32 gates' adjoints.  The 4-qubit-window form (complex64,
+ * L >= 14) replays the adjoints of its FP32 window matrices, which matches
+ * forwards run segment by segment as fl_apply_period(ctx, psi, K) (or one
+ * fl_apply_period(n_periods) when K == 0).  The 6-qubit window forms replay
+ * gate by gate; with K > 0 their dE/dT carries ~1e-3 (FP32 windows) to
+ * ~1e-2 (split-BF16x3) relative error, so take their gradients with K == 0.
  * Synchronises. */
 int fl_grad(fl_ctx *ctx, void *psi_n, void *const *ckpts, int64_t n_periods, int64_t K, const double *gens, int P,
             void *lambda_ws, double *grad);
@@ -230,6 +239,18 @@ int fl_tile_map(int L, int dtype, int h, uint64_t *out);
  * complex, frag_out (if not NULL) the 4 KiB of FP32 fragments of the real
  * 32x32 form. */
 int fl_host_window_matrix(const double *G, const int *pos, int nops, int mode, double *U_out, void *frag_out);
+
+/* The overlap terms of the reverse pass for one 4-bit register group, from
+ * its window overlap Q[x][y] = sum_r psi_{r,x} conj(lambda_{r,y}) ([16][16]
+ * complex, taken before the group's first op; window index bit i = tile bit
+ * u0 + i) and its ops: op k applies G[k] ([nops][4][4] complex, local index
+ * 2 bit(pos+1) + bit(pos)) on window bits (pos[k], pos[k]+1), pos in [0, 2].
+ * out[k][16]: the 16 reals of the op's bond at the state before its gate,
+ * [0..3] = Im(conj(lambda_l) psi_l), then (re, im) of
+ * sum conj(lambda_l) psi_m - conj(psi_l) lambda_m for the local index pairs
+ * 01, 02, 03, 12, 13, 23 (the anti-Hermitian part of the bond's overlap
+ * matrix, which the gradient of Sec. V's reverse replay needs).  FP64. */
+int fl_host_window_overlaps(const double *Q, const double *G, const int *pos, int nops, double *out);
 
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
  * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover on

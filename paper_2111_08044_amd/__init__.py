@@ -27,7 +27,7 @@ __all__ = [
     "fl_expect_energy", "fl_expect_energy_noalloc", "fl_energy_spread", "fl_overlap", "fl_grad_workspace_bytes", "fl_grad",
     "fl_last_error", "fl_xyz_bonds", "fl_xyz_generators", "fl_host_gates", "fl_host_gate_derivative",
     "fl_host_ground_states",
-    "fl_plan_query", "fl_tile_map", "fl_host_window_matrix", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
+    "fl_plan_query", "fl_tile_map", "fl_host_window_matrix", "fl_host_window_overlaps", "Context", "new_state", "FloquetEngine", "FloquetEnergy",
     "thermalization_rate", "fit_exponential_rate",
 ]
 
@@ -276,6 +276,19 @@ def fl_host_window_matrix(G, pos, mode=None):
                                       -1 if mode is None else int(mode), _dp(U.view(np.float64)),
                                       frag.ctypes.data_as(C.c_void_p) if frag is not None else None))
     return U, frag
+
+
+def fl_host_window_overlaps(Q, G, pos) -> np.ndarray:
+    """(nops, 16) overlap terms of a reverse register group from its 16x16
+    window overlap Q and its ops (gates G (nops, 4, 4) on window bits pos)."""
+    G = np.asarray(G, dtype=np.complex128).reshape(-1, 4, 4)
+    n = G.shape[0]
+    Qb = _c16(Q, (16, 16))
+    Gb = _c16(G, (n, 4, 4))
+    p = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
+    out = np.zeros((n, 16))
+    check(lib().fl_host_window_overlaps(_dp(Qb), _dp(Gb), p.ctypes.data_as(C.POINTER(C.c_int)), n, _dp(out)))
+    return out
 
 
 def fl_plan_query(L: int, dtype="c64", kind: int = 0, n: int = 1, dagger: bool = False) -> np.ndarray:

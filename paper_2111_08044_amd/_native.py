@@ -46,6 +46,7 @@ SIGNATURES = {
     "fl_xyz_generators": (C.c_int, [C.c_int, dp]),
     "fl_tile_map": (C.c_int, [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_uint64)]),
     "fl_host_window_matrix": (C.c_int, [dp, C.POINTER(C.c_int), C.c_int, C.c_int, dp, vp]),
+    "fl_host_window_overlaps": (C.c_int, [dp, dp, C.POINTER(C.c_int), C.c_int, dp]),
     "fl_plan_query": (C.c_int, [C.c_int, C.c_int, C.c_int, i64, C.c_int, C.POINTER(C.c_int32), i64,
                                 C.POINTER(i64)]),
 }

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -47,6 +48,7 @@ constexpr int kPlanBlock = 16;        // periods per planned block
 constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
+constexpr int kWin4Grid = 256;        // workgroups of the 4-qubit-window reverse pass (one per CU)
 constexpr int kMinNoallocGrid = 256;  // fewest reduction workgroups fl_expect_energy_noalloc runs
 constexpr int kStageSlots = 8;        // pinned host staging slots for uploads
 constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 complex doubles (init tables)
@@ -71,6 +73,21 @@ struct fl_ctx {
     double* h_red = nullptr;   // pinned host copy
     void* d_tabs = nullptr;    // product-state factor tables
     double* d_mpart = nullptr; // gradient partials [kAdjGrid][L-1][16]
+    // complex64 reverse pass with window overlaps on the matrix cores:
+    // Reverse pass of the 4-qubit-window form (k_adjoint_win4): for the
+    // n-period forward plan, its passes and groups in reverse order with the
+    // adjoint window fragments, and per reverse group the ops it undoes.
+    struct AdjWin4 {
+        std::vector<fl_pass> rev;            // reverse passes (u0 of each group, tiles as the forward's)
+        std::vector<std::array<int8_t, FL_MAX_OPS>> pos;    // per reverse group: window positions of its ops,
+        std::vector<std::array<int16_t, FL_MAX_OPS>> bond;  // and their bonds, in the order the replay meets them
+        std::vector<int> nops;
+        void* d_mats = nullptr;              // 4 KiB of fragments per reverse group
+    };
+    std::map<int, AdjWin4> adj_w4;
+    double* d_qpart = nullptr; // per-workgroup window overlaps [kWin4Grid][FL_WIN4_MAX_GROUPS][512]
+    double* d_qsum = nullptr;  // window overlap of every group of the reverse plans [groups][512]
+    size_t qsum_cap = 0;       // doubles allocated at d_qsum
     // Uploads (gates, bond terms, init tables) are copied on the context
     // stream from pinned staging slots; slot k may be refilled once the copy
     // recorded by stage_ev[k] has run.
@@ -195,13 +212,17 @@ int stage_commit(fl_ctx* c, const Staged& st) {
     return FL_OK;
 }
 
-// Drop the dense window plans; kernels already enqueued may still read them.
+// Drop the dense window plans (also those of the reverse pass); kernels
+// already enqueued may still read them.
 int drop_dense_plans(fl_ctx* c) {
-    if (c->dense_plans.empty() && c->dense_host.empty()) return FL_OK;
+    if (c->dense_plans.empty() && c->dense_host.empty() && c->adj_w4.empty()) return FL_OK;
     FL_HIP(hipStreamSynchronize(c->stream));
     for (auto& kv : c->dense_plans)
         if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
     c->dense_plans.clear();
+    for (auto& kv : c->adj_w4)
+        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
+    c->adj_w4.clear();
     c->dense_host.clear();
     return FL_OK;
 }
@@ -281,10 +302,11 @@ int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
         return FL_OK;
     }
     const int nb = c->L - 1;
-    std::vector<fl_pass> plan = fl::plan_sweep(c->geom, n, dagger, false, kMaxGatesPerPass);
+    const bool d4 = c->variant == FL_DENSE4_FP32;
+    std::vector<fl_pass> plan = fl::plan_sweep(c->geom, n, dagger, false, kMaxGatesPerPass, nullptr,
+                                               d4 ? FL_WIN4_MAX_GROUPS : FL_MAX_GROUPS);
     size_t nwin = 0;
     for (const fl_pass& p : plan) nwin += p.ngroups;
-    const bool d4 = c->variant == FL_DENSE4_FP32;
     const int mode = c->variant == FL_DENSE6_FP32 ? 0 : 1;
     const size_t fbytes = d4 ? 4096 : 65536;   // fragments per window
     std::vector<unsigned char> frags(nwin * fbytes);
@@ -399,6 +421,119 @@ int run_reverse(fl_ctx* c, void* psi, void* lam, int64_t n) {
     return FL_OK;
 }
 
+// The 4-qubit-window form (complex64, full 13-bit tiles) replays its own
+// forward windows backwards on the matrix cores (k_adjoint_win4).
+bool use_win4_reverse(const fl_ctx* c) {
+    return c->dtype == FL_C64 && c->variant == FL_DENSE4_FP32 && c->geom.R == 4 && c->geom.C == FL_LOWBITS &&
+           c->geom.C + c->geom.W == FL_KMAX_C64;
+}
+
+// The reverse of the n-period forward plan of the 4-qubit-window form: its
+// passes and, within each, its groups in reverse order; group k (in that
+// order) gets the fragments of U^dagger at k * 4 KiB, the exact transposes of
+// the FP32 matrices the forward applied, and the list of ops it undoes.
+int get_adj_win4(fl_ctx* c, int n, const fl_ctx::AdjWin4** out) {
+    auto it = c->adj_w4.find(n);
+    if (it != c->adj_w4.end()) {
+        *out = &it->second;
+        return FL_OK;
+    }
+    // the plan build_dense_plan runs for the forward (same planner call)
+    const std::vector<fl_pass> fwd =
+        fl::plan_sweep(c->geom, n, false, false, kMaxGatesPerPass, nullptr, FL_WIN4_MAX_GROUPS);
+    const int nb = c->L - 1;
+    fl_ctx::AdjWin4 aw;
+    size_t nwin = 0;
+    for (const fl_pass& p : fwd) nwin += (size_t)p.ngroups;
+    std::vector<unsigned char> frags(std::max<size_t>(nwin, 1) * 4096);
+    std::vector<cd> U(256), Ud(256);
+    size_t w = 0;
+    for (size_t i = fwd.size(); i-- > 0;) {
+        const fl_pass& p = fwd[i];
+        fl_pass rp = p;
+        for (int gr = 0; gr < p.ngroups; ++gr, ++w) {
+            const int g = p.ngroups - 1 - gr;
+            const cd* gates[FL_MAX_OPS];
+            int pos[FL_MAX_OPS];
+            std::array<int8_t, FL_MAX_OPS> rpos{};
+            std::array<int16_t, FL_MAX_OPS> rbond{};
+            for (int k = 0; k < p.nops[g]; ++k) {
+                const int gi = p.opg[g][k];
+                if (gi < 0 || gi >= nb) return fail(FL_EINVAL, "internal: unexpected gate index in a forward plan");
+                gates[k] = &c->G[(size_t)gi * 16];
+                pos[k] = p.opi[g][k];
+                rpos[p.nops[g] - 1 - k] = (int8_t)p.opi[g][k];
+                rbond[p.nops[g] - 1 - k] = (int16_t)gi;
+            }
+            fl::window_matrix_bits(gates, pos, p.nops[g], 4, U.data());
+            for (int r = 0; r < 16; ++r)
+                for (int q = 0; q < 16; ++q) Ud[16 * r + q] = std::conj(U[16 * q + r]);
+            fl::window_fragments4(Ud.data(), reinterpret_cast<float*>(frags.data() + w * 4096));
+            rp.u0[gr] = p.u0[g];
+            rp.nops[gr] = p.nops[g];
+            aw.pos.push_back(rpos);
+            aw.bond.push_back(rbond);
+            aw.nops.push_back(p.nops[g]);
+        }
+        aw.rev.push_back(rp);
+    }
+    hipError_t e = hipMalloc(&aw.d_mats, frags.size());
+    if (e != hipSuccess) return fail(FL_ENOMEM, "reverse-pass windows: device allocation failed");
+    // stream-ordered; the host copy lives as long as the windows
+    c->dense_host.push_back(std::move(frags));
+    const auto& src = c->dense_host.back();
+    e = hipMemcpyAsync(aw.d_mats, src.data(), src.size(), hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(aw.d_mats);
+        c->dense_host.pop_back();
+        return fail_hip(e, "reverse-pass windows upload");
+    }
+    auto& slot = c->adj_w4[n];
+    slot = std::move(aw);
+    *out = &slot;
+    return FL_OK;
+}
+
+// Replay one reverse plan; its group k adds its window overlap to
+// d_qsum[(base + k) * 512 ...].
+int run_reverse_win4(fl_ctx* c, void* psi, void* lam, const fl_ctx::AdjWin4& aw, size_t base) {
+    const int grid = (int)std::min<uint32_t>(ntiles(c->geom), kWin4Grid);
+    const unsigned char* mats = static_cast<const unsigned char*>(aw.d_mats);
+    size_t k = 0;
+    for (const fl_pass& p : aw.rev) {
+        hipError_t e = fl::launch_adjoint_win4(c->geom, psi, lam, mats + k * 4096, p, c->d_qpart, grid,
+                                               c->d_qsum + (base + k) * 512, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_adjoint_win4 launch");
+        k += (size_t)p.ngroups;
+    }
+    return FL_OK;
+}
+
+// The bond overlap terms (16 reals per bond, summed) of every op undone by a
+// reverse plan, from its groups' window overlaps Q (host FP64, the FP64
+// adjoint gates).
+void overlap_terms_win4(const fl_ctx* c, const fl_ctx::AdjWin4& aw, const double* qsum, std::vector<double>& D) {
+    std::vector<cd> Gd((size_t)(c->L - 1) * 16);
+    for (int b = 0; b < c->L - 1; ++b)
+        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) Gd[(size_t)b * 16 + 4 * i + j] = std::conj(c->G[(size_t)b * 16 + 4 * j + i]);
+    cd Q[256];
+    double out[FL_MAX_OPS * 16];
+    for (size_t k = 0; k < aw.nops.size(); ++k) {
+        const double* q = qsum + k * 512;
+        for (int e = 0; e < 256; ++e) Q[e] = cd(q[e], q[256 + e]);
+        const cd* gates[FL_MAX_OPS];
+        int pos[FL_MAX_OPS];
+        for (int o = 0; o < aw.nops[k]; ++o) {
+            gates[o] = &Gd[(size_t)aw.bond[k][o] * 16];
+            pos[o] = aw.pos[k][o];
+        }
+        fl::window_overlap_terms(Q, gates, pos, aw.nops[k], out);
+        for (int o = 0; o < aw.nops[k]; ++o)
+            for (int v = 0; v < 16; ++v) D[(size_t)aw.bond[k][o] * 16 + v] += out[o * 16 + v];
+    }
+}
+
 int apply_h0(fl_ctx* c, const void* psi, void* out) {
     bool first = true;
     for (const fl_pass& p : c->cover) {
@@ -496,6 +631,8 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_red, (size_t)2 * L * 16 * sizeof(double), 0);
     if (e == hipSuccess) e = hipMalloc(&c->d_tabs, (size_t)3 * 4096 * 2 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&c->d_mpart, (size_t)kAdjGrid * nb * 16 * sizeof(double));
+    if (e == hipSuccess && use_win4_reverse(c))
+        e = hipMalloc((void**)&c->d_qpart, (size_t)kWin4Grid * FL_WIN4_MAX_GROUPS * 512 * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->h_stage, (size_t)kStageSlots * kStageBytes, 0);
     for (int k = 0; k < kStageSlots && e == hipSuccess; ++k)
         e = hipEventCreateWithFlags(&c->stage_ev[k], hipEventDisableTiming);
@@ -525,6 +662,10 @@ int fl_destroy(fl_ctx* c) {
     if (c->h_red) (void)hipHostFree(c->h_red);
     if (c->d_tabs) (void)hipFree(c->d_tabs);
     if (c->d_mpart) (void)hipFree(c->d_mpart);
+    for (auto& kv : c->adj_w4)
+        if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
+    if (c->d_qpart) (void)hipFree(c->d_qpart);
+    if (c->d_qsum) (void)hipFree(c->d_qsum);
     for (auto& kv : c->dense_plans)
         if (kv.second.d_mats) (void)hipFree(kv.second.d_mats);
     delete c;
@@ -814,19 +955,70 @@ int fl_grad(fl_ctx* c, void* psi_n, void* const* ckpts, int64_t n, int64_t K, co
     rc = apply_h0(c, psi_n, lam);
     if (rc) return rc;
     // 3. reverse replay with checkpoint resets, accumulating D_b
-    const int agrid = (int)std::min<uint32_t>(ntiles(c->geom_adj), kAdjGrid);
-    e = fl::launch_zero(c->d_mpart, (uint64_t)agrid * nb * 16, c->stream);
-    if (e != hipSuccess) return fail_hip(e, "k_zero launch");
-    for (int64_t s = nseg - 1; s >= 0; --s) {
-        rc = run_reverse(c, psi_n, lam, seglen);
-        if (rc) return rc;
-        if (K > 0) FL_HIP(hipMemcpyAsync(psi_n, ckpts[s], bytes, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<double> Dmx;   // the matrix-core path's bond terms (host FP64)
+    if (use_win4_reverse(c)) {
+        // A segment's forward was fl_apply_period(K): qb blocks of kPlanBlock
+        // periods, then the rr-period remainder; its replay runs the reverse
+        // of the remainder plan, then of the block plan qb times.
+        const int64_t qb = seglen / kPlanBlock, rr = seglen % kPlanBlock;
+        const fl_ctx::AdjWin4* pb = nullptr;
+        const fl_ctx::AdjWin4* pr = nullptr;
+        if (qb > 0) {
+            rc = get_adj_win4(c, kPlanBlock, &pb);
+            if (rc) return rc;
+        }
+        if (rr > 0) {
+            rc = get_adj_win4(c, (int)rr, &pr);
+            if (rc) return rc;
+        }
+        const size_t gb = pb ? pb->nops.size() : 0, gr = pr ? pr->nops.size() : 0;
+        const size_t need = std::max<size_t>(1, gb + gr) * 512;
+        if (need > c->qsum_cap) {
+            FL_HIP(hipStreamSynchronize(c->stream));
+            if (c->d_qsum) (void)hipFree(c->d_qsum);
+            c->d_qsum = nullptr;
+            c->qsum_cap = 0;
+            e = hipMalloc((void**)&c->d_qsum, need * sizeof(double));
+            if (e != hipSuccess) return fail(FL_ENOMEM, "window overlap sums: device allocation failed");
+            c->qsum_cap = need;
+        }
+        e = fl::launch_zero(c->d_qsum, need, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_zero launch");
+        for (int64_t s = nseg - 1; s >= 0; --s) {
+            if (pr) {
+                rc = run_reverse_win4(c, psi_n, lam, *pr, gb);
+                if (rc) return rc;
+            }
+            for (int64_t i = 0; i < qb; ++i) {
+                rc = run_reverse_win4(c, psi_n, lam, *pb, 0);
+                if (rc) return rc;
+            }
+            if (K > 0) FL_HIP(hipMemcpyAsync(psi_n, ckpts[s], bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+        std::vector<double> qsum(need);
+        FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, (size_t)L * 16 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+        FL_HIP(hipMemcpyAsync(qsum.data(), c->d_qsum, need * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        FL_HIP(hipStreamSynchronize(c->stream));
+        Dmx.assign((size_t)nb * 16, 0.0);
+        if (pb) overlap_terms_win4(c, *pb, qsum.data(), Dmx);
+        if (pr) overlap_terms_win4(c, *pr, qsum.data() + gb * 512, Dmx);
+    } else {
+        const int agrid = (int)std::min<uint32_t>(ntiles(c->geom_adj), kAdjGrid);
+        e = fl::launch_zero(c->d_mpart, (uint64_t)agrid * nb * 16, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_zero launch");
+        for (int64_t s = nseg - 1; s >= 0; --s) {
+            rc = run_reverse(c, psi_n, lam, seglen);
+            if (rc) return rc;
+            if (K > 0) FL_HIP(hipMemcpyAsync(psi_n, ckpts[s], bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+        e = fl::launch_finalize(c->d_mpart, agrid, nb * 16, c->d_red + (size_t)L * 16, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
+        FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, (size_t)2 * L * 16 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+        FL_HIP(hipStreamSynchronize(c->stream));
     }
-    e = fl::launch_finalize(c->d_mpart, agrid, nb * 16, c->d_red + (size_t)L * 16, c->stream);
-    if (e != hipSuccess) return fail_hip(e, "k_finalize launch");
-    FL_HIP(hipMemcpyAsync(c->h_red, c->d_red, (size_t)2 * L * 16 * sizeof(double), hipMemcpyDeviceToHost,
-                          c->stream));
-    FL_HIP(hipStreamSynchronize(c->stream));
+    const double* Dsrc = Dmx.empty() ? c->h_red + (size_t)L * 16 : Dmx.data();
     // 4. contractions on the host (FP64):
     //    dE/dtheta_{b,p} = Re sum_ij A_ij D_ij + tr(gen rho_b),  A = (dG/dtheta) G^dagger
     //    dE/dT          = sum_b Re sum_ij (-(i/2) h_b)_ij D_ij
@@ -835,7 +1027,7 @@ int fl_grad(fl_ctx* c, void* psi_n, void* const* ckpts, int64_t n, int64_t K, co
     for (int b = 0; b < nb; ++b) {
         cd rho[16], D[16];
         rho_from16(c->h_red + (size_t)b * 16, rho);
-        const double* v = c->h_red + (size_t)L * 16 + (size_t)b * 16;
+        const double* v = Dsrc + (size_t)b * 16;
         for (int i = 0; i < 4; ++i) D[5 * i] = cd(0.0, 2.0 * v[i]);
         int k = 4;
         for (int i = 0; i < 4; ++i)
@@ -985,6 +1177,21 @@ int fl_host_window_matrix(const double* G, const int* pos, int nops, int mode, d
     return FL_OK;
 }
 
+int fl_host_window_overlaps(const double* Q, const double* G, const int* pos, int nops, double* out) {
+    if (!Q || !G || !pos || nops < 0 || nops > 64 || !out) return fail(FL_EINVAL, "bad argument");
+    for (int k = 0; k < nops; ++k)
+        if (pos[k] < 0 || pos[k] > 2) return fail(FL_EINVAL, "gate position outside a 4-bit window");
+    std::vector<cd> q(256), g((size_t)nops * 16);
+    for (int e = 0; e < 256; ++e) q[e] = cd(Q[2 * e], Q[2 * e + 1]);
+    std::vector<const cd*> gp(nops);
+    for (int k = 0; k < nops; ++k) {
+        read_c16(G + (size_t)k * 32, &g[(size_t)k * 16]);
+        gp[k] = &g[(size_t)k * 16];
+    }
+    fl::window_overlap_terms(q.data(), gp.data(), pos, nops, out);
+    return FL_OK;
+}
+
 int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* buf, int64_t cap, int64_t* needed) {
     if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "bad dtype");
     if (L < 2 || L > (dtype == FL_C64 ? 34 : 33)) return fail(FL_EINVAL, "L out of range");
@@ -996,8 +1203,9 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
         g = fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
-        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
-        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass);
+        const int mg = kind == 5 ? FL_WIN4_MAX_GROUPS : FL_MAX_GROUPS;
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
         for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
         plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 1) {
@@ -1017,8 +1225,9 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
         g = fl::make_geom(L, FL_KMAX_C64, kind == 4 ? 6 : 4);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
-        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
-        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass);
+        const int mg = kind == 5 ? FL_WIN4_MAX_GROUPS : FL_MAX_GROUPS;
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
         for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
         plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 3) {

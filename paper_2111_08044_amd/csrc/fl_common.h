@@ -35,6 +35,8 @@
 #define FL_KMAX_C64 13       // tile bits for complex64 (64 KiB of LDS)
 #define FL_KMAX_C128 12      // tile bits for complex128 (64 KiB of LDS)
 #define FL_KMAX_ADJ 12       // tile bits of the two-state adjoint pass (complex64)
+#define FL_WIN4_MAX_GROUPS 14  // register groups per pass of a 4-qubit-window plan (the reverse pass keeps one window-overlap sum per group)
+#define FL_WIN4_NT 512         // threads of the 4-qubit-window reverse pass (13-bit tiles of two states)
 #define FL_KMAX_RDM 12       // tile bits of the energy / density-matrix reduction
 #define FL_MAX_SLOTS 16      // distinct reduction slots per pass
 #ifndef FL_SWEEP_NT_C64
@@ -97,6 +99,13 @@ FL_HD uint64_t fl_tile_offset(uint32_t j, int C, int h) {
 // of pairwise tile loads hit 16 distinct 8-byte slots within each run of 16
 // lanes.  The function is linear over XOR: slot(a ^ b) = slot(a) ^ slot(b).
 FL_HD uint32_t fl_swz(uint32_t j) { return j ^ ((j >> 4) & 15u); }
+
+// The same folding of bits 8..11 as well (also linear over XOR): for 12-bit
+// tiles, 16 lanes that step through a 4-bit window's amplitudes at stride
+// 2^u0 then hit 16 distinct 8-byte slots for every u0, as do the column and
+// pairwise patterns fl_swz serves (the reverse pass with window overlaps on
+// the matrix cores reads its tiles both ways).
+FL_HD uint32_t fl_swz12(uint32_t j) { return j ^ ((j >> 4) & 15u) ^ ((j >> 8) & 15u); }
 
 // Insert R zero bits at position u0 into o.
 FL_HD uint32_t fl_spread(uint32_t o, int u0, int R) {

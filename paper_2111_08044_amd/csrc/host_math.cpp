@@ -199,6 +199,60 @@ void window_matrix(const cd* const* gates, const int* pos, int nops, cd* U) {
     window_matrix_bits(gates, pos, nops, 6, U);
 }
 
+// 4-bit window index with bits (i, i+1) = the local index a (bit i = a & 1)
+// and the other two bits = z, in order.
+static inline int ins2(int a, int z, int i) {
+    const int lo = z & ((1 << i) - 1);
+    const int hi = z >> i;
+    return lo | (a << i) | (hi << (i + 2));
+}
+
+void window_overlap_terms(const cd* Q, const cd* const* gates, const int* pos, int nops, double* out) {
+    // T = the 16x16 window overlap sum psi_x conj(lambda_y) before op k; the
+    // op's gate G (local index 2 bit(i+1) + bit(i)) then maps T to G T G^dagger.
+    cd T[256], U[256];
+    for (int e = 0; e < 256; ++e) T[e] = Q[e];
+    for (int k = 0; k < nops; ++k) {
+        const int i = pos[k];
+        // R[a][b] = sum over the other two window bits of T
+        cd R[16];
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                cd s = 0.0;
+                for (int z = 0; z < 4; ++z) s += T[ins2(a, z, i) * 16 + ins2(b, z, i)];
+                R[4 * a + b] = s;
+            }
+        // sum conj(lambda_l) psi_m - conj(psi_l) lambda_m = R[m][l] - conj(R[l][m]);
+        // the diagonal keeps Im R[l][l] (half of the purely imaginary entry)
+        double* o = out + (size_t)k * 16;
+        for (int l = 0; l < 4; ++l) o[l] = R[5 * l].imag();
+        int q = 4;
+        for (int l = 0; l < 4; ++l)
+            for (int m = l + 1; m < 4; ++m) {
+                const cd d = R[4 * m + l] - std::conj(R[4 * l + m]);
+                o[q] = d.real();
+                o[q + 1] = d.imag();
+                q += 2;
+            }
+        // T <- G T G^dagger on window bits (i, i+1)
+        const cd* G = gates[k];
+        for (int z = 0; z < 4; ++z)
+            for (int y = 0; y < 16; ++y)
+                for (int a = 0; a < 4; ++a) {
+                    cd s = 0.0;
+                    for (int a2 = 0; a2 < 4; ++a2) s += G[4 * a + a2] * T[ins2(a2, z, i) * 16 + y];
+                    U[ins2(a, z, i) * 16 + y] = s;
+                }
+        for (int x = 0; x < 16; ++x)
+            for (int z = 0; z < 4; ++z)
+                for (int b = 0; b < 4; ++b) {
+                    cd s = 0.0;
+                    for (int b2 = 0; b2 < 4; ++b2) s += U[x * 16 + ins2(b2, z, i)] * std::conj(G[4 * b + b2]);
+                    T[x * 16 + ins2(b, z, i)] = s;
+                }
+    }
+}
+
 void window_fragments4(const cd* U, float* out) {
     // real form A[2m'+c'][2m+c] of the 16x16 complex U with its columns taken
     // component-major, k' = 16 c + m: lane l, step s holds A[l % 32][k] for

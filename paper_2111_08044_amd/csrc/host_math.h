@@ -32,6 +32,17 @@ void window_matrix_bits(const std::complex<double>* const* gates, const int* pos
 // The 6-bit case (U: 64x64).
 void window_matrix(const std::complex<double>* const* gates, const int* pos, int nops, std::complex<double>* U);
 
+// Overlap terms of the ops of one 4-bit register group of the reverse pass,
+// from the group's window overlap Q[x][y] = sum_r psi_{r,x} conj(lambda_{r,y})
+// (16x16 complex, row-major) taken before its first op.  Op k applies
+// gates[k] (4x4, local index 2 bit(pos+1) + bit(pos)) on window bits
+// (pos[k], pos[k]+1); out[k][16] receives its bond's terms at the state before
+// the gate, in the reverse kernel's layout: [0..3] Im(conj(lambda_l) psi_l),
+// then (re, im) of sum conj(lambda_l) psi_m - conj(psi_l) lambda_m for the
+// pairs 01, 02, 03, 12, 13, 23.
+void window_overlap_terms(const std::complex<double>* Q, const std::complex<double>* const* gates, const int* pos,
+                          int nops, double* out);
+
 // MFMA fragments of the real 32x32 form of a 16x16 complex window matrix
 // (k = 2m + (0 re, 1 im)): out[lane * 16 + s] = A[lane % 32][2 s + lane / 32],
 // 1024 floats (4 KiB).

@@ -25,6 +25,13 @@ hipError_t launch_apply_h(int dtype, const fl_geom& g, const void* psi, void* la
                           int first, hipStream_t s);
 hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, const void* gates, const fl_pass& pd,
                           double* Mpart, int grid, hipStream_t s);
+// reverse pass of the 4-qubit-window form (complex64, full 13-bit tiles) on
+// the matrix cores: mats = the pass's window fragments (4 KiB per group, the
+// transposes of the forward's), Qpart [grid][FL_WIN4_MAX_GROUPS][512]
+// per-workgroup scratch, Qsum [pass groups][512] += the pass's window
+// overlaps (Re, Im of 16x16)
+hipError_t launch_adjoint_win4(const fl_geom& g, void* psi, void* lam, const void* mats, const fl_pass& pd,
+                               double* Qpart, int grid, double* Qsum, hipStream_t s);
 hipError_t launch_zero(double* p, uint64_t n, hipStream_t s);
 // 4-qubit windows on FP32 MFMA; full tiles only (C + W = 13); mats: 4 KiB of fragments per window
 hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl_pass& pd, hipStream_t s);

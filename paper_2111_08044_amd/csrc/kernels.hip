@@ -35,6 +35,10 @@ template <typename T> struct CT;
 template <> struct CT<float> { typedef float2 c; };
 template <> struct CT<double> { typedef double2 c; };
 
+typedef float fl_f32x4 __attribute__((ext_vector_type(4)));
+typedef float fl_f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 fl_bf16x8 __attribute__((ext_vector_type(8)));
+
 // ---------------------------------------------------------------------------
 // register-level gate application
 // ---------------------------------------------------------------------------
@@ -206,7 +210,13 @@ __device__ __forceinline__ void apply_op(T (&vr)[1 << R], T (&vi)[1 << R], int i
 // tile load / store (global <-> LDS), 16-byte global accesses
 // ---------------------------------------------------------------------------
 
-template <typename T, int KT, int NT = FL_NT>
+// LDS slot of tile element j: fl_swz (SW = 0) or fl_swz12 (SW = 1)
+template <int SW>
+__device__ __forceinline__ uint32_t tile_swz(uint32_t j) {
+    return SW ? fl_swz12(j) : fl_swz(j);
+}
+
+template <typename T, int KT, int NT = FL_NT, int SW = 0>
 __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C,
                                           int h, typename CT<T>::c* lds) {
     typedef typename CT<T>::c cplx;
@@ -223,15 +233,15 @@ __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ 
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
                 const uint32_t j = 2u * (threadIdx.x + s * NT);
-                lds[fl_swz(j)] = make_float2(v[s].x, v[s].y);
-                lds[fl_swz(j + 1)] = make_float2(v[s].z, v[s].w);
+                lds[tile_swz<SW>(j)] = make_float2(v[s].x, v[s].y);
+                lds[tile_swz<SW>(j + 1)] = make_float2(v[s].z, v[s].w);
             }
         } else {
             for (int p = threadIdx.x; p < n2; p += NT) {
                 const uint32_t j = 2u * p;
                 const float4 v = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
-                lds[fl_swz(j)] = make_float2(v.x, v.y);
-                lds[fl_swz(j + 1)] = make_float2(v.z, v.w);
+                lds[tile_swz<SW>(j)] = make_float2(v.x, v.y);
+                lds[tile_swz<SW>(j + 1)] = make_float2(v.z, v.w);
             }
         }
     } else {
@@ -245,14 +255,14 @@ __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ 
                 v[s] = psi[base + fl_tile_offset(j, C, h)];
             }
 #pragma unroll
-            for (int s = 0; s < ITER; ++s) lds[fl_swz(threadIdx.x + s * NT)] = v[s];
+            for (int s = 0; s < ITER; ++s) lds[tile_swz<SW>(threadIdx.x + s * NT)] = v[s];
         } else {
-            for (int j = threadIdx.x; j < n; j += NT) lds[fl_swz(j)] = psi[base + fl_tile_offset(j, C, h)];
+            for (int j = threadIdx.x; j < n; j += NT) lds[tile_swz<SW>(j)] = psi[base + fl_tile_offset(j, C, h)];
         }
     }
 }
 
-template <typename T, int KT, int NT = FL_NT>
+template <typename T, int KT, int NT = FL_NT, int SW = 0>
 __device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, uint64_t base, int K, int C, int h,
                                            const typename CT<T>::c* lds) {
     if constexpr (sizeof(T) == 4) {
@@ -262,19 +272,19 @@ __device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, 
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
                 const uint32_t j = 2u * (threadIdx.x + s * NT);
-                const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
+                const float2 a = lds[tile_swz<SW>(j)], b = lds[tile_swz<SW>(j + 1)];
                 *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
             }
         } else {
             for (int p = threadIdx.x; p < n2; p += NT) {
                 const uint32_t j = 2u * p;
-                const float2 a = lds[fl_swz(j)], b = lds[fl_swz(j + 1)];
+                const float2 a = lds[tile_swz<SW>(j)], b = lds[tile_swz<SW>(j + 1)];
                 *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
             }
         }
     } else {
         const int n = 1 << K;
-        for (int j = threadIdx.x; j < n; j += NT) psi[base + fl_tile_offset(j, C, h)] = lds[fl_swz(j)];
+        for (int j = threadIdx.x; j < n; j += NT) psi[base + fl_tile_offset(j, C, h)] = lds[tile_swz<SW>(j)];
     }
 }
 
@@ -1438,6 +1448,255 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(T) ==
     }
 }
 
+// The reverse pass of the gradient for the 4-qubit-window form (complex64,
+// full 13-bit tiles), on the matrix cores.  The forward pass of that form
+// applies, per register group (a 4-bit window whose ops q = 0 .. n-1 apply
+// G_q inside the window), the FP32 real form of U = G_{n-1} ... G_0.  This
+// kernel replays the same passes backwards, groups in reverse order, with the
+// transposes of those FP32 matrices, i.e. the exact adjoints U^dagger of what
+// the forward applied, so psi retraces the forward's states up to arithmetic
+// rounding (as the plain form's replay with the adjoints of its FP32 gates
+// does) and a reset from a checkpoint does not jump.  Per group:
+//  - the window overlap Q[x][y] = sum_r psi_{r,x} conj(lambda_{r,y}) of the
+//    state after the forward group, as the real 32 x 32 product
+//    D[2x + a][2y + b] = sum_c psi_{x,a}(c) lambda_{y,b}(c) over the wave's
+//    64 columns c (a, b = re, im) on v_mfma_f32_32x32x2f32: lane l supplies
+//    row i = l % 32 of psi and column j = l % 32 of lambda at column k = l / 32
+//    of the step, the same LDS position in both tiles.  Then
+//    Re Q = D[2x][2y] + D[2x+1][2y+1] and Im Q = D[2x+1][2y] - D[2x][2y+1],
+//    formed between neighbouring lanes and summed over the workgroup's tiles
+//    in LDS (FP32, one 2 KiB row per group of the pass).  Every forward op's
+//    bond overlap follows from Q: with the reverse ops r = 0 .. n-1 applying
+//    G_{n-1-r}^dagger, the state before reverse op r is P_r Q P_r^dagger
+//    (P_r the product of the reverse ops before it), traced over the two
+//    window bits off the bond; the host forms these terms in FP64;
+//  - U^dagger on psi and on lambda as in k_dense4 (mats: 4 KiB of A fragments
+//    per group of the reverse pass, B = a 32-column block of the state).
+// Wave w owns columns 64 w .. 64 w + 63 of the group (column = the tile bits
+// off the window, in order) for both parts, so a barrier is needed only where
+// the next group assigns the tile's elements to the waves differently.  The
+// tiles use the slots of fl_swz12, under which the Q reads (lanes along the
+// window's amplitudes) and the column reads meet at most two distinct
+// addresses per bank.  At the end Qpart[blockIdx][g][0..255] = Re Q[x][y] at
+// 16 x + y, [256..511] = Im Q (FP64 copies of the FP32 sums).
+__global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2))) void k_adjoint_win4(
+    float2* __restrict__ psi, float2* __restrict__ lam, const float4* __restrict__ mats, int W, uint32_t ntiles,
+    fl_pass pd, double* __restrict__ Qpart) {
+    constexpr int K = FL_KMAX_C64;
+    constexpr int C = FL_LOWBITS;
+    constexpr int NT = FL_WIN4_NT;
+    constexpr int NW = NT / 64;
+    constexpr int KC = K - 4;                   // column bits of a group
+    constexpr int NB = (1 << KC) / (32 * NW);   // 32-column blocks per wave
+    constexpr int WB = __builtin_ctz(NW);       // column bits that name the wave
+    constexpr int NG = FL_WIN4_MAX_GROUPS;
+    constexpr int IT = (1 << (K - 1)) / NT;     // 16-byte tile accesses per thread and state
+    static_assert(NB == 2 && (1 << KC) == 64 * NW, "a wave owns 64 columns");
+    __shared__ __attribute__((aligned(16))) float2 lp[1 << K];
+    __shared__ __attribute__((aligned(16))) float2 ll[1 << K];
+    __shared__ float qacc[NG][512];
+    const int h = pd.h;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lc = lane & 31, lk = lane >> 5;
+    for (int t = threadIdx.x; t < NG * 512; t += NT) (&qacc[0][0])[t] = 0.f;
+    char* const pb = reinterpret_cast<char*>(lp);
+    char* const lb = reinterpret_cast<char*>(ll);
+    auto load_a = [&](int g, float (&dst)[16]) {
+        const float4* M = mats + (size_t)g * 256 + (size_t)lane * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float4 t = M[q];
+            dst[4 * q] = t.x;
+            dst[4 * q + 1] = t.y;
+            dst[4 * q + 2] = t.z;
+            dst[4 * q + 3] = t.w;
+        }
+    };
+    // tile element pairs (2 (tid + s NT), + 1) of both states, through
+    // registers, so that the next tile's psi loads run under the current
+    // tile's last group
+    float4 tp[IT], tl[IT];
+    auto fetch = [&](uint32_t tile, const float2* __restrict__ src, float4 (&dst)[IT]) {
+        const uint64_t base = fl_tile_base(tile, C, W, h);
+#pragma unroll
+        for (int s = 0; s < IT; ++s)
+            dst[s] = *reinterpret_cast<const float4*>(src + base + fl_tile_offset(2u * (threadIdx.x + s * NT), C, h));
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int s = 0; s < IT; ++s) {
+            const uint32_t j = 2u * (threadIdx.x + s * NT);
+            lp[fl_swz12(j)] = make_float2(tp[s].x, tp[s].y);
+            lp[fl_swz12(j + 1)] = make_float2(tp[s].z, tp[s].w);
+            ll[fl_swz12(j)] = make_float2(tl[s].x, tl[s].y);
+            ll[fl_swz12(j + 1)] = make_float2(tl[s].z, tl[s].w);
+        }
+    };
+    // the wave's columns are 64 w + (0 .. 63); which tile bits name the wave
+    // depends only on how many of column bits KC - WB .. KC - 1 lie below u0
+    auto part = [](int u) { return u <= KC - WB ? 0 : u - (KC - WB); };
+    const float qsgn = (lc & 1) ? -1.0f : 1.0f;
+    if (blockIdx.x < ntiles) {
+        fetch(blockIdx.x, psi, tp);
+        fetch(blockIdx.x, lam, tl);
+        put();
+    }
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint32_t next = tile + gridDim.x;
+        bool fetched = false;
+        __syncthreads();
+        float a[16], an[16];
+        if (pd.ngroups > 0) load_a(0, a);
+        for (int g = 0; g < pd.ngroups; ++g) {
+            const int u0 = pass_u0(pd, g);
+            load_a(g + 1 < pd.ngroups ? g + 1 : g, an);
+            // (1) window overlap.  Step s takes columns 64 w + 2 s + k;
+            // element spread(64 w + lk) | (lc >> 1) << u0 | spread(2 s)
+            // (disjoint bits), component lc & 1: a per-lane byte offset XOR a
+            // uniform one.
+            const uint32_t ql = (fl_swz12(fl_spread((uint32_t)(64 * w + lk), u0, 4) | ((uint32_t)(lc >> 1) << u0)) * 8u) |
+                                (4u * (uint32_t)(lc & 1));
+            auto read_q = [&](int h0, float (&qx)[16], float (&qy)[16]) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int st = h0 + i;
+                    const uint32_t o =
+                        ql ^ __builtin_amdgcn_readfirstlane(fl_swz12(fl_spread((uint32_t)(2 * st), u0, 4)) * 8u);
+                    qx[i] = *reinterpret_cast<const float*>(pb + o);
+                    qy[i] = *reinterpret_cast<const float*>(lb + o);
+                }
+            };
+            // (2) B operands of U^dagger on psi: amplitude 2t + lk of the
+            // lane's column in block cb
+            uint32_t vb[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) vb[cb] = fl_swz12(fl_spread((uint32_t)(64 * w + 32 * cb + lc), u0, 4)) * 8u;
+            const uint32_t lkoff = fl_swz12((uint32_t)lk << u0) * 8u;
+            auto read_b = [&](const char* sb, float (&bq)[16][NB]) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const uint32_t ss = fl_swz12((uint32_t)(2 * t) << u0) * 8u;
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb) {
+                        const float2 x = *reinterpret_cast<const float2*>(sb + ((vb[cb] ^ lkoff) ^ ss));
+                        bq[t][cb] = x.x;
+                        bq[t + 8][cb] = x.y;
+                    }
+                }
+            };
+            auto apply_u = [&](char* sb, const float (&bq)[16][NB]) {
+                fl_f32x16 acc[NB];
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[cb][r] = 0.0f;
+#pragma unroll
+                for (int st = 0; st < 16; ++st)
+#pragma unroll
+                    for (int cb = 0; cb < NB; ++cb)
+                        acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], bq[st][cb], acc[cb], 0, 0, 0);
+                // register r of block cb holds row 8 (r / 4) + 4 lk + r % 4 = 2 m + c
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) {
+                            const uint32_t m = 4 * q + 2 * lk + p;
+                            float2 v;
+                            v.x = acc[cb][4 * q + 2 * p];
+                            v.y = acc[cb][4 * q + 2 * p + 1];
+                            *reinterpret_cast<float2*>(sb + (vb[cb] ^ (fl_swz12(m << u0) * 8u))) = v;
+                        }
+            };
+            {
+                fl_f32x16 dq;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) dq[r] = 0.0f;
+#pragma unroll
+                for (int hh = 0; hh < 2; ++hh) {
+                    float qa[16], qb[16];
+                    read_q(16 * hh, qa, qb);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) dq = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[i], qb[i], dq, 0, 0, 0);
+                }
+                // register r of dq is row 8 (r / 4) + 4 lk + r % 4 of D; rows
+                // (r, r + 1), r even, are window amplitude x = 4 (r / 4) + 2 lk +
+                // (r % 4) / 2, components re, im, and this lane's column is
+                // (y, b) = (lc >> 1, lc & 1).  With t = register r + 1 of the
+                // neighbouring lane, b = 0 forms Re Q = D[2x][2y] + t and b = 1
+                // forms Im Q = t - D[2x][2y+1].
+#pragma unroll
+                for (int pr = 0; pr < 8; ++pr) {
+                    const int r = 2 * pr;
+                    const float t = fl_dpp_f<0xB1>(dq[r + 1]);   // quad_perm(1,0,3,2): lane ^ 1
+                    const float v = fmaf(qsgn, dq[r], t);
+                    const int x = 4 * (pr >> 1) + 2 * lk + (pr & 1);
+                    __hip_atomic_fetch_add(&qacc[g][(lc & 1) * 256 + 16 * x + (lc >> 1)], v, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+            }
+            // the next tile's psi loads run under the last group's MFMAs
+            if (g + 1 == pd.ngroups && next < ntiles) {
+                fetch(next, psi, tp);
+                fetched = true;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            // (2) U^dagger on psi, then (3) on lambda
+#pragma unroll
+            for (int sidx = 0; sidx < 2; ++sidx) {
+                char* const sb = sidx ? lb : pb;
+                float bq[16][NB];
+                read_b(sb, bq);
+                apply_u(sb, bq);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (g + 1 == pd.ngroups || part(pass_u0(pd, g + 1)) != part(u0))
+                __syncthreads();
+            else
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < 16; ++k) a[k] = an[k];
+        }
+        const uint64_t base = fl_tile_base(tile, C, W, h);
+        tile_store<float, K, NT, 1>(psi, base, K, C, h, lp);
+        tile_store<float, K, NT, 1>(lam, base, K, C, h, ll);
+        if (next < ntiles) {
+            if (!fetched) fetch(next, psi, tp);
+            fetch(next, lam, tl);
+            __syncthreads();   // every wave has read the tile out of LDS
+            put();
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < pd.ngroups * 512; t += NT)
+        Qpart[(size_t)blockIdx.x * NG * 512 + t] = (double)(&qacc[0][0])[t];
+}
+
+// Qsum[t] += sum over the workgroups of Qpart[b][t] (t < nvals).  A block
+// takes 32 consecutive values; its thread (v, j) sums rows b = j, j + 8, ...
+// of value v (coalesced 256-byte rows), then the 8 partial sums of each value
+// are added in j order, so the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_qsum(const double* __restrict__ Qpart, int nblocks, int nvals,
+                                              double* __restrict__ Qsum) {
+    __shared__ double part[8][32];
+    const int v = threadIdx.x & 31, j = threadIdx.x >> 5;
+    const int t = blockIdx.x * 32 + v;
+    double s = 0.0;
+    if (t < nvals) {
+#pragma unroll 8
+        for (int b = j; b < nblocks; b += 8) s += Qpart[(size_t)b * FL_WIN4_MAX_GROUPS * 512 + t];
+    }
+    part[j][v] = s;
+    __syncthreads();
+    if (j == 0 && t < nvals) {
+        double r = part[0][v];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) r += part[k][v];
+        Qsum[t] += r;
+    }
+}
+
 __global__ void k_zero(double* __restrict__ p, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0.0;
@@ -1460,8 +1719,6 @@ __global__ void k_zero(double* __restrict__ p, uint64_t n) {
 // A fragments arrive pre-arranged per (wave, lane): MODE 0 as 64 floats
 // (step kk = k/2), MODE 1 as 8 steps x 8 bf16 for hi, then the same for lo.
 
-typedef float fl_f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 fl_bf16x8 __attribute__((ext_vector_type(8)));
 
 #define FL_DENSE_PLANE_STRIDE 136   // bf16 per column of a split plane (128 + 8 pad)
 
@@ -1965,6 +2222,18 @@ hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, con
             hipLaunchKernelGGL((k_adjoint<double, 2, 0, FL_KMAX_ADJ>), dim3(grid), dim3(FL_NT), 0, s, p, l, G, g.C,
                                g.W, nt, pd, Mpart, nb);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_win4(const fl_geom& g, void* psi, void* lam, const void* mats, const fl_pass& pd,
+                               double* Qpart, int grid, double* Qsum, hipStream_t s) {
+    if (g.K != FL_KMAX_C64 || g.R != 4 || g.C != FL_LOWBITS || g.C + g.W != FL_KMAX_C64 ||
+        pd.ngroups > FL_WIN4_MAX_GROUPS || grid < 1)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_adjoint_win4, dim3(grid), dim3(FL_WIN4_NT), 0, s, (float2*)psi, (float2*)lam,
+                       (const float4*)mats, g.W, ntiles_of(g), pd, Qpart);
+    const int nvals = pd.ngroups * 512;
+    if (nvals > 0) hipLaunchKernelGGL(k_qsum, dim3((nvals + 31) / 32), dim3(256), 0, s, Qpart, grid, nvals, Qsum);
     return hipGetLastError();
 }
 

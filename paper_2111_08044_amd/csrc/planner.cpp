@@ -85,10 +85,10 @@ std::vector<int> run_tile(const fl_geom& g, int h, Sched& s, int cap) {
 // Pack an ordered gate list into register groups.  A gate may join the
 // current group only if no earlier gate left for later shares one of its
 // bits (then it commutes with everything it overtakes).  Returns the gates
-// that did not fit into FL_MAX_GROUPS groups.
-std::vector<Gate> pack_groups(const fl_geom& g, std::vector<Gate> rem, fl_pass& pd) {
+// that did not fit into max_groups groups.
+std::vector<Gate> pack_groups(const fl_geom& g, std::vector<Gate> rem, fl_pass& pd, int max_groups) {
     pd.ngroups = 0;
-    while (!rem.empty() && pd.ngroups < FL_MAX_GROUPS) {
+    while (!rem.empty() && pd.ngroups < max_groups) {
         int best_u0 = -1;
         std::vector<int> best;
         for (int u0 = 0; u0 + g.R <= g.K; ++u0) {
@@ -216,7 +216,8 @@ int greedy_passes(const fl_geom& g, const std::vector<int>& windows, Sched s, in
 }  // namespace
 
 std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_slots,
-                                int max_gates_per_pass, PlanStats* st) {
+                                int max_gates_per_pass, PlanStats* st, int max_groups) {
+    if (max_groups < 1 || max_groups > FL_MAX_GROUPS) max_groups = FL_MAX_GROUPS;
     std::vector<fl_pass> plan;
     const int L = g.L, nb = L - 1;
     Sched s;
@@ -266,7 +267,7 @@ std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_
         fl_pass pd;
         std::memset(&pd, 0, sizeof(pd));
         pd.h = best_h;
-        std::vector<Gate> left = pack_groups(g, gl, pd);
+        std::vector<Gate> left = pack_groups(g, gl, pd, max_groups);
 #if !defined(FL_NO_BALANCE)
         balance_groups(g, pd);
 #endif

@@ -21,9 +21,11 @@ struct PlanStats {
 // With with_slots, every op also names a reduction slot (local to the pass,
 // pass.sbond maps it to the bond; used by the reverse pass of the gradient,
 // which accumulates a bond's overlap matrix right before undoing that
-// bond's gate).  The tile must hold at most FL_MAX_SLOTS bonds.
+// bond's gate).  The tile must hold at most FL_MAX_SLOTS bonds.  A pass has
+// at most max_groups register groups (gates that do not fit wait for a later
+// pass).
 std::vector<fl_pass> plan_sweep(const fl_geom& g, int n, bool dagger, bool with_slots,
-                                int max_gates_per_pass, PlanStats* st = nullptr);
+                                int max_gates_per_pass, PlanStats* st = nullptr, int max_groups = FL_MAX_GROUPS);
 
 // Passes that visit every bond exactly once (one group per bond, op slot =
 // global bond index, no gate); the first pass has flags = 1 (also reduce the

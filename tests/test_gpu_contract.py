@@ -142,6 +142,78 @@ def test_gradient_c4_config_fp32_against_fp64_gpu():
     assert err < 1e-3
 
 
+# ------------------------------------- gradient of the 4-qubit-window form
+
+@pytest.mark.parametrize("L,n,K,tol", [(14, 200, 50, 1e-4), (16, 200, 50, 3e-4), (14, 50, 10, 1e-4),
+                                       (16, 37, 0, 1e-4), (15, 21, 7, 1e-4)])
+def test_gradient_dense4_matches_oracle_adjoint(L, n, K, tol):
+    """The 4-qubit-window form (FP32 MFMA windows forward, their exact
+    adjoints replayed on the matrix cores with the window-overlap terms)
+    against the FP64 oracle adjoint: at the configured depth n = 200, K = 50,
+    with many checkpoint resets (K = 10), with none (K = 0), and with
+    segments that end in a partial plan block (K = 7).  Relative error of the
+    largest component <= 1e-4; at L = 16, n = 200 the plain form's own FP32
+    error is 1.7e-4, so there the bound is 3e-4.  (A replay with windows that
+    are not the exact adjoints of the forward's FP32 matrices misses these
+    bounds by an order of magnitude once checkpoints reset psi: 1.1e-3 at
+    L = 14, n = 200, K = 50.)"""
+    say(f"case: grad dense4 L={L} n={n} K={K}")
+    w, hs = _model(L, seed=61)
+    gens = O.xyz_coupling_generators(L)
+    ref, Eref = O.adjoint_gradient(L, hs, gens, w["T"], O.product_state(w["spinors"]), n)
+    ctx = fl.fl_create(L, "c64", "dense4_fp32")
+    fl.fl_set_bonds(ctx, hs, w["T"])
+    psi = fl.new_state(ctx)
+    fl.fl_init_state(ctx, psi, w["spinors"])
+    ck = []
+    if K > 0:
+        for _ in range(n // K):
+            ck.append(psi.clone())
+            fl.fl_apply_period(ctx, psi, K)
+    else:
+        fl.fl_apply_period(ctx, psi, n)
+    E, N = fl.fl_expect_energy(ctx, psi)
+    g = fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi))
+    err = np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    say(f"grad dense4 L={L} n={n} K={K}: rel err {err:.3e} (dE/dT {g[-1]:.6f} vs {ref[-1]:.6f}), "
+        f"|E-Eref|/L {abs(E - Eref) / L:.3e}")
+    fl.fl_destroy(ctx)
+    assert abs(E - Eref) / L < 1e-5
+    assert err < tol
+
+
+def test_gradient_c4_config_dense4_against_fp64_gpu():
+    """The adjoint workload (L = 24, n = 200, K = 50) in the 4-qubit-window
+    form against the complex128 GPU gradient: relative error <= 1e-4, E_n
+    within 1e-5 per site."""
+    L, n, K = 24, 200, 50
+    say(f"case: grad C4 dense4 L={L} n={n} K={K}")
+    w, hs = _model(L)
+    gens = O.xyz_coupling_generators(L)
+    out = {}
+    for dt, va in (("c128", "plain"), ("c64", "dense4_fp32")):
+        ctx = fl.fl_create(L, dt, va)
+        fl.fl_set_bonds(ctx, fl.fl_xyz_bonds(L, w["J"], w["fields"]), w["T"])
+        psi = fl.new_state(ctx)
+        fl.fl_init_state(ctx, psi, w["spinors"])
+        ck = []
+        for _ in range(n // K):
+            ck.append(psi.clone())
+            fl.fl_apply_period(ctx, psi, K)
+        E, N = fl.fl_expect_energy(ctx, psi)
+        out[dt] = (fl.fl_grad(ctx, psi, ck, n, K, gens, torch.empty_like(psi)), E / N)
+        del psi, ck
+        fl.fl_destroy(ctx)
+        torch.cuda.empty_cache()
+    g64, e64 = out["c128"]
+    g32, e32 = out["c64"]
+    err = np.max(np.abs(g32 - g64)) / np.max(np.abs(g64))
+    say(f"grad C4 dense4: rel err {err:.3e} (max |g| {np.max(np.abs(g64)):.3e}), |dE|/L {abs(e32 - e64) / L:.3e}, "
+        f"dE/dT {g32[-1]:.6f} vs {g64[-1]:.6f}")
+    assert abs(e32 - e64) / L < 1e-5
+    assert err < 1e-4
+
+
 def test_autograd_interleaved_forwards_use_their_own_couplings():
     """Two forwards on one engine with different couplings, then one
     backward through both: each gradient is the oracle's for its own J."""

@@ -401,3 +401,41 @@ def test_dense4_plan_is_the_brickwork_circuit(L, n, dagger):
     assert R == 4 and C + W == 13
     seq = pt.gate_sequence(L, words)
     pt.check_trace_equivalent(L, [b for b, _, _ in seq], n, dagger)
+
+
+def _window_apply(v, nout, i, G):
+    """Apply G (local index 2 bit(i+1) + bit(i)) on bits (i, i+1) of the low
+    4-bit window of a (2^nout * 16)-vector."""
+    w = v.reshape(1 << nout, 2 ** (2 - i), 2, 2, 1 << i)    # [r, high window bits, bit i+1, bit i, low bits]
+    loc = w.reshape(1 << nout, 2 ** (2 - i), 4, 1 << i)       # local index 2 bit(i+1) + bit(i)
+    return np.einsum("ab,xhbl->xhal", G, loc).reshape(-1)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_window_overlaps_match_direct_per_op_sums(seed):
+    """The reverse pass's overlap terms of a register group from one 16x16
+    window overlap Q, against the per-op sums taken directly on the states
+    between the gates (what the per-op reverse kernel accumulates)."""
+    rng = np.random.default_rng(seed)
+    nout, nops = 3, 6
+    n = (1 << nout) * 16
+    psi = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    lam = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    G = fin.random_unitaries(nops, 4, seed + 10)
+    pos = rng.integers(0, 3, nops)
+    P, Lm = psi.reshape(1 << nout, 16), lam.reshape(1 << nout, 16)
+    Q = P.T @ Lm.conj()                                        # Q[x][y] = sum_r psi_{r,x} conj(lambda_{r,y})
+    got = fl.fl_host_window_overlaps(Q, G, pos)
+    p, l = psi.copy(), lam.copy()
+    for k in range(nops):
+        i = int(pos[k])
+        loc = lambda v: v.reshape(1 << nout, 2 ** (2 - i), 4, 1 << i)
+        M = np.einsum("xhal,xhbl->ab", loc(l).conj(), loc(p))    # M[a][b] = sum conj(lambda_a) psi_b
+        ref = [M[a, a].imag for a in range(4)]
+        for a in range(4):
+            for b in range(a + 1, 4):
+                d = M[a, b] - np.conj(M[b, a])
+                ref += [d.real, d.imag]
+        assert np.max(np.abs(got[k] - np.array(ref))) < 1e-12, k
+        p = _window_apply(p, nout, i, G[k])
+        l = _window_apply(l, nout, i, G[k])
