@@ -78,7 +78,7 @@ struct fl_ctx {
     // n-period forward plan, its passes and groups in reverse order with the
     // adjoint window fragments, and per reverse group the ops it undoes.
     struct AdjWin4 {
-        std::vector<fl_pass> rev;            // reverse passes (u0 of each group, tiles as the forward's)
+        std::vector<fl_pass> rev;            // reverse passes: the forward's tiles, groups and ops in reverse order (G^dagger)
         std::vector<std::array<int8_t, FL_MAX_OPS>> pos;    // per reverse group: window positions of its ops,
         std::vector<std::array<int16_t, FL_MAX_OPS>> bond;  // and their bonds, in the order the replay meets them
         std::vector<int> nops;
@@ -469,8 +469,14 @@ int get_adj_win4(fl_ctx* c, int n, const fl_ctx::AdjWin4** out) {
             for (int r = 0; r < 16; ++r)
                 for (int q = 0; q < 16; ++q) Ud[16 * r + q] = std::conj(U[16 * q + r]);
             fl::window_fragments4(Ud.data(), reinterpret_cast<float*>(frags.data() + w * 4096));
+            // the reverse pass's group gr: the forward group g, ops reversed
             rp.u0[gr] = p.u0[g];
             rp.nops[gr] = p.nops[g];
+            for (int k = 0; k < p.nops[g]; ++k) {
+                rp.opi[gr][k] = p.opi[g][p.nops[g] - 1 - k];
+                rp.opg[gr][k] = (int16_t)(nb + p.opg[g][p.nops[g] - 1 - k]);   // G^dagger in the gate table
+                rp.ops[gr][k] = p.ops[g][p.nops[g] - 1 - k];
+            }
             aw.pos.push_back(rpos);
             aw.bond.push_back(rbond);
             aw.nops.push_back(p.nops[g]);
