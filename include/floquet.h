@@ -191,9 +191,10 @@ int64_t fl_grad_workspace_bytes(const fl_ctx *ctx);
  * replays the FP32 gates' adjoints.  The 4-qubit-window form (complex64,
  * L >= 14) replays the adjoints of its FP32 window matrices, which matches
  * forwards run segment by segment as fl_apply_period(ctx, psi, K) (or one
- * fl_apply_period(n_periods) when K == 0).  The 6-qubit window forms replay
- * gate by gate; with K > 0 their dE/dT carries ~1e-3 (FP32 windows) to
- * ~1e-2 (split-BF16x3) relative error, so take their gradients with K == 0.
+ * fl_apply_period(n_periods) when K == 0).  The 6-qubit window forms (and
+ * the 4-qubit one at L = 13) replay gate by gate; with K > 0 their dE/dT
+ * carries ~1e-3 (FP32 windows) to ~1e-2 (split-BF16x3) relative error, so
+ * take their gradients with K == 0.
  * Synchronises. */
 int fl_grad(fl_ctx *ctx, void *psi_n, void *const *ckpts, int64_t n_periods, int64_t K, const double *gens, int P,
             void *lambda_ws, double *grad);
