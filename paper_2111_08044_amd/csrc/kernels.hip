@@ -1584,8 +1584,7 @@ __global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2)))
                     }
                 }
             };
-            auto apply_u = [&](char* sb, const float (&bq)[16][NB]) {
-                fl_f32x16 acc[NB];
+            auto mfma_u = [&](const float (&bq)[16][NB], fl_f32x16 (&acc)[NB]) {
 #pragma unroll
                 for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -1595,7 +1594,9 @@ __global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2)))
 #pragma unroll
                     for (int cb = 0; cb < NB; ++cb)
                         acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], bq[st][cb], acc[cb], 0, 0, 0);
-                // register r of block cb holds row 8 (r / 4) + 4 lk + r % 4 = 2 m + c
+            };
+            // register r of block cb holds row 8 (r / 4) + 4 lk + r % 4 = 2 m + c
+            auto write_u = [&](char* sb, const fl_f32x16 (&acc)[NB]) {
 #pragma unroll
                 for (int cb = 0; cb < NB; ++cb)
 #pragma unroll
@@ -1609,17 +1610,39 @@ __global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2)))
                             *reinterpret_cast<float2*>(sb + (vb[cb] ^ (fl_swz12(m << u0) * 8u))) = v;
                         }
             };
+            // The phases in order, each one's LDS traffic placed between the
+            // previous one's MFMAs (the scheduler pins 2 MFMAs : 1 LDS access):
+            // Q reads A | Q MFMAs A + Q reads B | Q MFMAs B + psi reads |
+            // Q sums | psi MFMAs + lambda reads | lambda MFMAs + psi writes |
+            // lambda writes.  Each wave touches only its own columns, and its
+            // LDS accesses run in program order.
+            float bp[16][NB], bl[16][NB];
+            fl_f32x16 ap[NB], al[NB];
             {
                 fl_f32x16 dq;
 #pragma unroll
                 for (int r = 0; r < 16; ++r) dq[r] = 0.0f;
+                float qa[16], qb[16], qc[16], qd[16];
+                read_q(0, qa, qb);
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int hh = 0; hh < 2; ++hh) {
-                    float qa[16], qb[16];
-                    read_q(16 * hh, qa, qb);
+                for (int i = 0; i < 16; ++i) dq = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[i], qb[i], dq, 0, 0, 0);
+                read_q(16, qc, qd);
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) dq = __builtin_amdgcn_mfma_f32_32x32x2f32(qa[i], qb[i], dq, 0, 0, 0);
+                for (int i = 0; i < 16; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);   // DS read
                 }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) dq = __builtin_amdgcn_mfma_f32_32x32x2f32(qc[i], qd[i], dq, 0, 0, 0);
+                read_b(pb, bp);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 1);   // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 1);   // DS read
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 // register r of dq is row 8 (r / 4) + 4 lk + r % 4 of D; rows
                 // (r, r + 1), r even, are window amplitude x = 4 (r / 4) + 2 lk +
                 // (r % 4) / 2, components re, im, and this lane's column is
@@ -1642,15 +1665,25 @@ __global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2)))
                 fetched = true;
             }
             __builtin_amdgcn_sched_barrier(0);
-            // (2) U^dagger on psi, then (3) on lambda
+            // (2) U^dagger on psi, with lambda's reads in between
+            mfma_u(bp, ap);
+            read_b(lb, bl);
 #pragma unroll
-            for (int sidx = 0; sidx < 2; ++sidx) {
-                char* const sb = sidx ? lb : pb;
-                float bq[16][NB];
-                read_b(sb, bq);
-                apply_u(sb, bq);
-                __builtin_amdgcn_sched_barrier(0);
+            for (int i = 0; i < 16; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 2);   // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 2);   // DS read
             }
+            __builtin_amdgcn_sched_barrier(0);
+            // (3) U^dagger on lambda, with psi's writes in between
+            mfma_u(bl, al);
+            write_u(pb, ap);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 3);   // MFMA
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 3);   // DS write
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            write_u(lb, al);
             if (g + 1 == pd.ngroups || part(pass_u0(pd, g + 1)) != part(u0))
                 __syncthreads();
             else
@@ -2006,24 +2039,22 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 2)
         float bq[16][NB];
         // amplitude 2t + lk of the column: slot(spread(col)) ^ slot(lk << u0) ^ slot(2t << u0)
         const uint32_t lkoff = fl_swz((uint32_t)lk << u0) * 8u;
+        auto read_b = [&](int cb) {
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const uint32_t ss = fl_swz((uint32_t)(2 * t) << u0) * 8u;
-#pragma unroll
-            for (int cb = 0; cb < NB; ++cb) {
+            for (int t = 0; t < 8; ++t) {
+                const uint32_t ss = fl_swz((uint32_t)(2 * t) << u0) * 8u;
                 const float2 x = *reinterpret_cast<const float2*>(lbytes + ((vb[cb] ^ lkoff) ^ ss));
                 bq[t][cb] = x.x;
                 bq[t + 8][cb] = x.y;
             }
-        }
+        };
+        auto mfma_b = [&](int cb) {
 #pragma unroll
-        for (int st = 0; st < 16; ++st)
-#pragma unroll
-            for (int cb = 0; cb < NB; ++cb)
+            for (int st = 0; st < 16; ++st)
                 acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st], bq[st][cb], acc[cb], 0, 0, 0);
+        };
         // register r of block cb holds row 8(r/4) + 4 lk + r%4 = 2m' + c'
-#pragma unroll
-        for (int cb = 0; cb < NB; ++cb)
+        auto write_b = [&](int cb) {
 #pragma unroll
             for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -2034,6 +2065,38 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 2)
                     v.y = acc[cb][4 * q + 2 * p + 1];
                     *reinterpret_cast<float2*>(reinterpret_cast<char*>(lds) + (vb[cb] ^ (fl_swz(m << u0) * 8u))) = v;
                 }
+        };
+        // Blocks in two halves, so that the LDS traffic of one half runs
+        // under the MFMAs of the other: read the first half, then its MFMAs
+        // with the second half's reads in between, then the second half's
+        // MFMAs with the first half's writes in between, then those writes.
+        // (Each block reads and writes only its own columns.)
+        constexpr int HB = NB / 2;
+#pragma unroll
+        for (int cb = 0; cb < HB; ++cb) read_b(cb);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cb = 0; cb < HB; ++cb) mfma_b(cb);
+#pragma unroll
+        for (int cb = HB; cb < NB; ++cb) read_b(cb);
+#pragma unroll
+        for (int i = 0; i < 8 * HB; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // DS read
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cb = HB; cb < NB; ++cb) mfma_b(cb);
+#pragma unroll
+        for (int cb = 0; cb < HB; ++cb) write_b(cb);
+#pragma unroll
+        for (int i = 0; i < 8 * HB; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 1);   // MFMA
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 1);   // DS write
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int cb = HB; cb < NB; ++cb) write_b(cb);
         // the WB tile bits that select a wave's columns: column bits 9 - WB .. 8,
         // which sit 4 higher when at or above the window, so the set depends
         // only on how many of them lie below u0
