@@ -235,8 +235,9 @@ int fl_tile_map(int L, int dtype, int h, uint64_t *out);
  * complex) embedded at window bits (pos[k], pos[k]+1), window index bit i =
  * tile bit u0 + i, gate local index 2*bit(pos+1) + bit(pos).
  * mode -1, 0, 1: 6-bit window, U_out [64][64] complex; if frag_out is not
- * NULL it receives the 64 KiB of MFMA fragments of the real 128x128 form for
- * mode 0 (FP32) or 1 (bf16 hi/lo).  mode 2: 4-bit window, U_out [16][16]
+ * NULL it receives the MFMA fragments of the real 128x128 form: mode 0, 64 KiB
+ * of FP32; mode 1, 32 KiB of bf16 hi/lo (Re, Im) pairs of U, each stored once
+ * (the kernel forms the rows (Re, -Im) and (Im, Re)).  mode 2: 4-bit window, U_out [16][16]
  * complex, frag_out (if not NULL) the 4 KiB of FP32 fragments of the real
  * 32x32 form. */
 int fl_host_window_matrix(const double *G, const int *pos, int nops, int mode, double *U_out, void *frag_out);

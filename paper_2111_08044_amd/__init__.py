@@ -263,15 +263,17 @@ def fl_host_ground_states(h):
 
 def fl_host_window_matrix(G, pos, mode=None):
     """(U, fragments) of a dense window: U = E(op_n-1)...E(op_0) and, for mode
-    0/1 (6-bit window, U 64x64), the 64 KiB of MFMA fragments as raw bytes;
-    mode 2: 4-bit window, U 16x16, 4 KiB of FP32 fragments."""
+    0/1 (6-bit window, U 64x64), the MFMA fragments as raw bytes (mode 0:
+    64 KiB FP32, mode 1: 32 KiB of bf16 hi/lo (Re, Im) pairs); mode 2: 4-bit
+    window, U 16x16, 4 KiB of FP32 fragments."""
     G = np.asarray(G, dtype=np.complex128)
     n = G.shape[0]
     Gb = _c16(G, (n, 4, 4))
     p = np.ascontiguousarray(np.asarray(pos, dtype=np.int32))
     dim = 16 if mode == 2 else 64
     U = np.zeros((dim, dim), dtype=np.complex128)
-    frag = np.zeros(4096 if mode == 2 else 65536, dtype=np.uint8) if mode is not None else None
+    frag = (np.zeros({0: 65536, 1: 32768, 2: 4096}.get(int(mode), 65536), dtype=np.uint8)
+            if mode is not None else None)
     check(lib().fl_host_window_matrix(_dp(Gb), p.ctypes.data_as(C.POINTER(C.c_int)), n,
                                       -1 if mode is None else int(mode), _dp(U.view(np.float64)),
                                       frag.ctypes.data_as(C.c_void_p) if frag is not None else None))

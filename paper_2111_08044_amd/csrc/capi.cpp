@@ -308,7 +308,7 @@ int build_dense_plan(fl_ctx* c, int n, bool dagger, fl_ctx::DensePlan** out) {
     size_t nwin = 0;
     for (const fl_pass& p : plan) nwin += p.ngroups;
     const int mode = c->variant == FL_DENSE6_FP32 ? 0 : 1;
-    const size_t fbytes = d4 ? 4096 : 65536;   // fragments per window
+    const size_t fbytes = d4 ? 4096 : (mode == 1 ? 32768 : 65536);   // fragments per window
     std::vector<unsigned char> frags(nwin * fbytes);
     std::vector<cd> U(64 * 64);
     std::vector<cd> Gd((size_t)nb * 16);

@@ -299,19 +299,27 @@ void window_fragments(const cd* U, int mode, void* out) {
                 for (int kk = 0; kk < 64; ++kk)
                     o[(w * 64 + l) * 64 + kk] = (float)A(32 * w + (l & 31), 2 * kk + (l >> 5));
     } else {
+        // Rows 2m' and 2m'+1 of the real form hold the same numbers, (Re, -Im)
+        // and (Im, Re) of U[m'][m] at columns (2m, 2m+1); store each (Re, Im)
+        // pair once, split hi/lo, and let the kernel negate or swap per row.
+        // Chunk ((w * 8 + st) * 2 + lk) * 16 + mm holds, for m' = 16 w + mm,
+        // the pairs of m = 8 st + 4 lk .. + 3 (8 bf16); hi plane, then lo.
         uint16_t* hi = static_cast<uint16_t*>(out);
-        uint16_t* lo = hi + 16384;
+        uint16_t* lo = hi + 8192;
         for (int w = 0; w < 4; ++w)
-            for (int l = 0; l < 64; ++l)
-                for (int st = 0; st < 8; ++st)
-                    for (int i = 0; i < 8; ++i) {
-                        const double a = A(32 * w + (l & 31), 16 * st + 8 * (l >> 5) + i);
-                        const double h = bf16_rne(a);
-                        const double lw = bf16_rne(a - h);
-                        const size_t idx = (size_t)((w * 64 + l) * 8 + st) * 8 + i;
-                        hi[idx] = bf16_bits(h);
-                        lo[idx] = bf16_bits(lw);
-                    }
+            for (int st = 0; st < 8; ++st)
+                for (int lk = 0; lk < 2; ++lk)
+                    for (int mm = 0; mm < 16; ++mm)
+                        for (int j = 0; j < 4; ++j) {
+                            const cd u = U[(16 * w + mm) * 64 + 8 * st + 4 * lk + j];
+                            const size_t idx = ((size_t)((w * 8 + st) * 2 + lk) * 16 + mm) * 8 + 2 * j;
+                            const double parts[2] = {u.real(), u.imag()};
+                            for (int c = 0; c < 2; ++c) {
+                                const double h = bf16_rne(parts[c]);
+                                hi[idx + c] = bf16_bits(h);
+                                lo[idx + c] = bf16_bits(bf16_rne(parts[c] - h));
+                            }
+                        }
     }
 }
 

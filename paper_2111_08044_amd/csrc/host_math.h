@@ -52,10 +52,14 @@ void window_fragments4(const std::complex<double>* U, float* out);
 double bf16_rne(double a);
 
 // Per-lane MFMA fragments of the real 128x128 form of a 64x64 complex window
-// matrix (rows/columns ordered k = 2m + (0 re, 1 im)).  mode 0: 16384 floats,
-// [wave][lane][kk] = A[32 wave + lane%32][2 kk + lane/32].  mode 1: 16384
-// uint16 bf16 hi then 16384 lo, [wave][lane][step][i] =
-// A[32 wave + lane%32][16 step + 8 (lane/32) + i].  out: 64 KiB.
+// matrix (rows/columns ordered k = 2m + (0 re, 1 im)).  mode 0: 16384 floats
+// (64 KiB), [wave][lane][kk] = A[32 wave + lane%32][2 kk + lane/32].  mode 1:
+// the (Re, Im) pairs of U, each stored once (rows 2m' and 2m'+1 of A hold the
+// same numbers), 8192 uint16 bf16 hi then 8192 lo (32 KiB):
+// [wave][step][lk][mm][j][c] = part c of U[16 wave + mm][8 step + 4 lk + j];
+// a lane with row 32 wave + lane%32 = 2m' + c' takes its 8 values
+// A[2m'+c'][16 step + 8 lk + i] as (Re, -Im) pairs for c' = 0, (Im, Re) for 1.
+void window_fragments(const std::complex<double>* U, int mode, void* out);
 void window_fragments(const std::complex<double>* U, int mode, void* out);
 
 // Factor tables of a product state psi[x] = thi[x >> (a+b)] tmid[(x >> a) & (2^b-1)] tlo[x & (2^a-1)].

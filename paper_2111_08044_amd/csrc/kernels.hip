@@ -1902,15 +1902,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                                 otid + __builtin_amdgcn_readfirstlane(plane_off(256u * (uint32_t)t, u0)));
             __syncthreads();
         }
-        // A fragments of a window: 8 steps x 8 bf16 for hi, then for lo
+        // A fragments of a window: 8 steps x 8 bf16 for hi, then for lo.  The
+        // window stores each (Re, Im) pair of U once (32 KiB): lanes 2m' and
+        // 2m'+1 of a half-wave load the same 16 bytes, and row 2m' takes them
+        // as (Re, -Im), row 2m'+1 as (Im, Re): a rotation by 16 bits per lane
+        // parity, then a sign flip of the high half for the even rows.
         fl_bf16x8 ah[8], al[8];
+        const uint32_t rot = 16u * (uint32_t)(lane & 1);
+        const uint32_t neg = (lane & 1) ? 0u : 0x80000000u;
+        auto fix = [&](const float4& t) {
+            uint4 u = *reinterpret_cast<const uint4*>(&t);
+            u.x = __builtin_amdgcn_alignbit(u.x, u.x, rot) ^ neg;
+            u.y = __builtin_amdgcn_alignbit(u.y, u.y, rot) ^ neg;
+            u.z = __builtin_amdgcn_alignbit(u.z, u.z, rot) ^ neg;
+            u.w = __builtin_amdgcn_alignbit(u.w, u.w, rot) ^ neg;
+            return *reinterpret_cast<const fl_bf16x8*>(&u);
+        };
         auto load_a = [&](int g) {
-            const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 4096 + (size_t)(w * 64 + lane) * 8;
+            const float4* M = mats + (size_t)pass_gate(pd, g, 0) * 2048 + (size_t)(w * 16 * 16 + lk * 16 + (lc >> 1));
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const float4 th = M[q], tl = M[2048 + q];
-                ah[q] = *reinterpret_cast<const fl_bf16x8*>(&th);
-                al[q] = *reinterpret_cast<const fl_bf16x8*>(&tl);
+                const float4 th = M[q * 32], tl = M[1024 + q * 32];
+                ah[q] = fix(th);
+                al[q] = fix(tl);
             }
         };
         if (ng > 0) load_a(0);

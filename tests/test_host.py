@@ -337,8 +337,23 @@ def test_window_fragments_layout_and_split(mode):
         ref = A[(32 * w + (l & 31))[..., None], (2 * kk[None, None, :] + (l >> 5)[..., None])]
         assert np.array_equal(f, ref.astype(np.float32).astype(np.float64))
     else:
-        h = _bits_to_f(frag[:32768].view(np.uint16)).reshape(4, 64, 8, 8)
-        lo = _bits_to_f(frag[32768:].view(np.uint16)).reshape(4, 64, 8, 8)
+        # stored: [wave][step][lk][mm][j][c] = part c of U[16 wave + mm][8 step + 4 lk + j]
+        assert frag.size == 32768
+        hs = _bits_to_f(frag[:16384].view(np.uint16)).reshape(4, 8, 2, 16, 4, 2)
+        ls = _bits_to_f(frag[16384:].view(np.uint16)).reshape(4, 8, 2, 16, 4, 2)
+        # the lane view the kernel forms: lane l (row 2m' + c', m' = 16 w + (l%32)//2,
+        # c' = l % 2, lk = l // 32) takes (Re, -Im) pairs for c' = 0, (Im, Re) for c' = 1
+        def lanes(p):
+            out = np.zeros((4, 64, 8, 8))
+            for ww in range(4):
+                for ll in range(64):
+                    mm, cr, lk = (ll & 31) >> 1, ll & 1, ll >> 5
+                    for stp in range(8):
+                        pr = p[ww, stp, lk, mm]              # (4, 2): (Re, Im) per j
+                        v = np.stack([pr[:, 0], -pr[:, 1]], 1) if cr == 0 else np.stack([pr[:, 1], pr[:, 0]], 1)
+                        out[ww, ll, stp] = v.reshape(8)
+            return out
+        h, lo = lanes(hs), lanes(ls)
         st, i = np.meshgrid(np.arange(8), np.arange(8), indexing="ij")
         rows = (32 * w + (l & 31))[..., None, None]
         cols = 16 * st[None, None] + 8 * (l >> 5)[..., None, None] + i[None, None]
