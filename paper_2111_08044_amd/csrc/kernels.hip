@@ -1773,7 +1773,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int ncb = FULL ? 4 : 1 << (K - 6 - 5);   // 32-column blocks (1, 2 or 4)
     const int ng = pd.ngroups;
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
-    tile_load<float, 0>(psi, base, K, C, h, lds);
+    // full tiles: the unrolled form, every thread's 16 loads in flight at once
+    if constexpr (FULL)
+        tile_load<float, KMAXD>(psi, base, K, C, h, lds);
+    else
+        tile_load<float, 0>(psi, base, K, C, h, lds);
     __syncthreads();
     // write Y (registers of one window) back to the FP32 tile: register r of
     // block cb holds row 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column
@@ -1981,7 +1985,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             __syncthreads();
         }
     }
-    tile_store<float, 0>(psi, base, K, C, h, lds);
+    if constexpr (FULL)
+        tile_store<float, KMAXD>(psi, base, K, C, h, lds);
+    else
+        tile_store<float, 0>(psi, base, K, C, h, lds);
 }
 
 // ---------------------------------------------------------------------------
