@@ -513,14 +513,15 @@ def test_fma_probe_computes_its_recurrence():
 
 # ----------------------------------------------------------------- degenerate depth
 
-@pytest.mark.parametrize("dtype", ["c64", "c128"])
-def test_zero_periods_is_the_identity_and_gradient_is_explicit(dtype):
+@pytest.mark.parametrize("dtype,variant", [("c64", "plain"), ("c128", "plain"), ("c64", "dense4_fp32")])
+def test_zero_periods_is_the_identity_and_gradient_is_explicit(dtype, variant):
     """n = 0: fl_apply_period leaves the state bit-identical; the gradient
-    then has only its explicit terms (Eq. (10) at t = 0), dE/dT = 0."""
+    then has only its explicit terms (Eq. (10) at t = 0), dE/dT = 0 (also
+    through the window form's replay, which then runs no pass)."""
     L = 14
-    say(f"case: zero periods {dtype} L={L}")
+    say(f"case: zero periods {dtype} {variant} L={L}")
     w, hs = _model(L, seed=53)
-    ctx = fl.fl_create(L, dtype)
+    ctx = fl.fl_create(L, dtype, variant)
     fl.fl_set_bonds(ctx, hs, w["T"])
     psi = fl.new_state(ctx)
     fl.fl_init_state(ctx, psi, w["spinors"])
