@@ -228,7 +228,10 @@ __device__ __forceinline__ void tile_load(const typename CT<T>::c* __restrict__ 
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
                 const uint32_t j = 2u * (threadIdx.x + s * NT);
-                v[s] = *reinterpret_cast<const float4*>(psi + base + fl_tile_offset(j, C, h));
+                // streaming: each amplitude is read once per pass
+                const fl_f32x4 t =
+                    __builtin_nontemporal_load(reinterpret_cast<const fl_f32x4*>(psi + base + fl_tile_offset(j, C, h)));
+                v[s] = make_float4(t[0], t[1], t[2], t[3]);
             }
 #pragma unroll
             for (int s = 0; s < ITER; ++s) {
@@ -273,7 +276,8 @@ __device__ __forceinline__ void tile_store(typename CT<T>::c* __restrict__ psi, 
             for (int s = 0; s < ITER; ++s) {
                 const uint32_t j = 2u * (threadIdx.x + s * NT);
                 const float2 a = lds[tile_swz<SW>(j)], b = lds[tile_swz<SW>(j + 1)];
-                *reinterpret_cast<float4*>(psi + base + fl_tile_offset(j, C, h)) = make_float4(a.x, a.y, b.x, b.y);
+                const fl_f32x4 t = {a.x, a.y, b.x, b.y};
+                __builtin_nontemporal_store(t, reinterpret_cast<fl_f32x4*>(psi + base + fl_tile_offset(j, C, h)));
             }
         } else {
             for (int p = threadIdx.x; p < n2; p += NT) {
