@@ -1004,7 +1004,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
         const float2* src = psi + fl_tile_base(tile, C, W, h) + toff;
         float4 v[ITER];
 #pragma unroll
-        for (int s = 0; s < ITER; ++s) v[s] = *reinterpret_cast<const float4*>(src + s * tstride);
+        for (int s = 0; s < ITER; ++s) {
+            // streaming: each amplitude is read once per pass
+            const fl_f32x4 t = __builtin_nontemporal_load(reinterpret_cast<const fl_f32x4*>(src + s * tstride));
+            v[s] = make_float4(t[0], t[1], t[2], t[3]);
+        }
         __syncthreads();   // the previous tile's LDS reads (and the accumulator reset) are done
 #pragma unroll
         for (int s = 0; s < ITER; ++s) {
