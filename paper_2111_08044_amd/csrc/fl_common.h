@@ -100,11 +100,11 @@ FL_HD uint64_t fl_tile_offset(uint32_t j, int C, int h) {
 // lanes.  The function is linear over XOR: slot(a ^ b) = slot(a) ^ slot(b).
 FL_HD uint32_t fl_swz(uint32_t j) { return j ^ ((j >> 4) & 15u); }
 
-// The same folding of bits 8..11 as well (also linear over XOR): for 12-bit
-// tiles, 16 lanes that step through a 4-bit window's amplitudes at stride
-// 2^u0 then hit 16 distinct 8-byte slots for every u0, as do the column and
-// pairwise patterns fl_swz serves (the reverse pass with window overlaps on
-// the matrix cores reads its tiles both ways).
+// The same folding of bits 8..11 as well (also linear over XOR): 16 lanes
+// that step through a 4-bit window's amplitudes at stride 2^u0 then hit 16
+// distinct 8-byte slots for every u0 of a 12-bit tile (and meet at most two
+// addresses per bank on 13-bit tiles), as do the column and pairwise patterns
+// fl_swz serves.  The window form's reverse pass reads its tiles both ways.
 FL_HD uint32_t fl_swz12(uint32_t j) { return j ^ ((j >> 4) & 15u) ^ ((j >> 8) & 15u); }
 
 // Insert R zero bits at position u0 into o.
