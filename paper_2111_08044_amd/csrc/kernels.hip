@@ -1764,7 +1764,10 @@ __global__ void k_zero(double* __restrict__ p, uint64_t n) {
 #define FL_DENSE_PLANE_STRIDE 136   // bf16 per column of a split plane (128 + 8 pad)
 
 // FULL: the tile has the full KMAXD = 13 bits (every chain with L >= 13), so
-// the column-block and element counts are compile-time constants.
+// the column-block and element counts are compile-time constants.  The FP32
+// tile uses the slots of fl_swz12: the 32 columns of a block read at one
+// window position then meet at most two addresses per bank even for windows
+// starting at bit 0, where fl_swz left them on 4 distinct slots.
 template <int MODE, bool FULL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_dense6(float2* __restrict__ psi, const float4* __restrict__ mats,
                                                 uint32_t ntiles, int C, int W, fl_pass pd) {
@@ -1783,9 +1786,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const uint64_t base = fl_tile_base(blockIdx.x, C, W, h);
     // full tiles: the unrolled form, every thread's 16 loads in flight at once
     if constexpr (FULL)
-        tile_load<float, KMAXD>(psi, base, K, C, h, lds);
+        tile_load<float, KMAXD, 256, 1>(psi, base, K, C, h, lds);
     else
-        tile_load<float, 0>(psi, base, K, C, h, lds);
+        tile_load<float, 0, 256, 1>(psi, base, K, C, h, lds);
     __syncthreads();
     // write Y (registers of one window) back to the FP32 tile: register r of
     // block cb holds row 32w + 8(r/4) + 4 lk + r%4 (= 2m' + c'), column
@@ -1796,7 +1799,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             if (cb < ncb) {
-                const uint32_t vb = fl_swz(cbase[cb]) * 8u;
+                const uint32_t vb = fl_swz12(cbase[cb]) * 8u;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
 #pragma unroll
@@ -1805,7 +1808,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         float2 v;
                         v.x = acc[cb][4 * q + 2 * p];
                         v.y = acc[cb][4 * q + 2 * p + 1];
-                        *reinterpret_cast<float2*>(smem + (vb ^ (fl_swz(m << u0) * 8u))) = v;
+                        *reinterpret_cast<float2*>(smem + (vb ^ (fl_swz12(m << u0) * 8u))) = v;
                     }
                 }
             }
@@ -1841,12 +1844,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             // lane's half (re for lk = 0, im for lk = 1) is 4 lk bytes further
             uint32_t bb[4];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) bb[cb] = fl_swz(cbase[cb]) * 8u + 4u * (uint32_t)lk;
+            for (int cb = 0; cb < 4; ++cb) bb[cb] = fl_swz12(cbase[cb]) * 8u + 4u * (uint32_t)lk;
             // B operands of step kk + 2 are read while step kk multiplies
             constexpr int PF = 2;
             float bq[PF + 1][4];
             auto fetch = [&](int kk, float (&dst)[4]) {
-                const uint32_t sk = fl_swz((uint32_t)kk << u0) * 8u;
+                const uint32_t sk = fl_swz12((uint32_t)kk << u0) * 8u;
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb)
                     if (cb < ncb) dst[cb] = *reinterpret_cast<const float*>(smem + (bb[cb] ^ sk));
@@ -1899,10 +1902,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             constexpr int PER = (1 << KMAXD) / 256;
             float2 mine[PER];
             const int nper = FULL ? PER : (1 << K) / 256;
-            const uint32_t l0 = fl_swz(threadIdx.x);   // fl_swz(tid + 256 t) = l0 + 256 t
+            const uint32_t l0 = fl_swz12(threadIdx.x);   // slot(tid + 256 t) = l0 ^ slot(256 t)
 #pragma unroll
             for (int t = 0; t < PER; ++t)
-                if (t < nper) mine[t] = lds[l0 + 256 * t];
+                if (t < nper) mine[t] = lds[l0 ^ fl_swz12(256u * (uint32_t)t)];
             __syncthreads();
             const int u0 = pass_u0(pd, 0);
             const uint32_t otid = plane_off(threadIdx.x, u0);
@@ -1994,9 +1997,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
     }
     if constexpr (FULL)
-        tile_store<float, KMAXD>(psi, base, K, C, h, lds);
+        tile_store<float, KMAXD, 256, 1>(psi, base, K, C, h, lds);
     else
-        tile_store<float, 0>(psi, base, K, C, h, lds);
+        tile_store<float, 0, 256, 1>(psi, base, K, C, h, lds);
 }
 
 // ---------------------------------------------------------------------------
