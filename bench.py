@@ -43,7 +43,7 @@ PEAK_FP32_VALU = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # WRITE_SIZE read 8.0 GiB -> x1).  Valid only for the kernel code it was taken
 # on: the key is a hash of kernels.hip and fl_common.h with comments and
 # whitespace removed.
-TRAFFIC = {"kernel_code_sha256_16": "21e90ba8b8b00c3d", "fetch_gib_raw": 4.0002, "fetch_scale": 2.0,
+TRAFFIC = {"kernel_code_sha256_16": "5db4bd0c229e19cb", "fetch_gib_raw": 4.0002, "fetch_scale": 2.0,
            "write_gib_raw": 8.0, "write_scale": 1.0}
 
 
