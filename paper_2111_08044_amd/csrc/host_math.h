@@ -60,7 +60,6 @@ double bf16_rne(double a);
 // a lane with row 32 wave + lane%32 = 2m' + c' takes its 8 values
 // A[2m'+c'][16 step + 8 lk + i] as (Re, -Im) pairs for c' = 0, (Im, Re) for 1.
 void window_fragments(const std::complex<double>* U, int mode, void* out);
-void window_fragments(const std::complex<double>* U, int mode, void* out);
 
 // Factor tables of a product state psi[x] = thi[x >> (a+b)] tmid[(x >> a) & (2^b-1)] tlo[x & (2^a-1)].
 void product_tables(int L, const std::complex<double>* spinors, int a, int b,
