@@ -226,7 +226,9 @@ int fl_host_gate_derivative(const double *h, const double *gen, double T, double
 int fl_xyz_generators(int L, double *gens_out);
 
 /* Amplitude index of tile-local element j of tile t for window start h, for
- * the tile geometry of dtype (out: 2^L uint64 values, out[t * 2^K + j]).
+ * the tile geometry of the plain sweep of dtype (complex64: 4 low bits and a
+ * 9-bit window; complex128: 6 low bits and a 6-bit window; a single tile when
+ * L is at most the tile size) (out: 2^L uint64 values, out[t * 2^K + j]).
  * Returns FL_EINVAL for L > 24 or an invalid window. */
 int fl_tile_map(int L, int dtype, int h, uint64_t *out);
 

@@ -48,12 +48,21 @@ constexpr int kPlanBlock = 16;        // periods per planned block
 constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pass
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
+constexpr int kAdjLowBits = 4;       // low tile bits of the reverse pass (its kernel takes C at run time)
 constexpr int kWin4Grid = 256;        // workgroups of the 4-qubit-window reverse pass (one per CU)
 constexpr int kMinNoallocGrid = 256;  // fewest reduction workgroups fl_expect_energy_noalloc runs
 constexpr int kStageSlots = 8;        // pinned host staging slots for uploads
 constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 complex doubles (init tables)
 
 int kmax_of(int dtype) { return dtype == FL_C64 ? FL_KMAX_C64 : FL_KMAX_C128; }
+
+// Geometry of the plain sweep: complex64 on 13-bit tiles with 4 low bits and
+// 5-bit register groups, complex128 on 12-bit tiles with 6 low bits and 4-bit
+// groups.
+fl_geom plain_geom(int L, int dtype) {
+    return dtype == FL_C64 ? fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64, FL_SWEEP_LOWBITS_C64)
+                           : fl::make_geom(L, FL_KMAX_C128, 4);
+}
 size_t amp_bytes(int dtype) { return dtype == FL_C64 ? 8 : 16; }
 
 }  // namespace
@@ -614,10 +623,10 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->variant = variant;
     c->dev = dev;
     c->stream = (hipStream_t)hip_stream;
-    c->geom = (variant == FL_PLAIN)         ? fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4)
+    c->geom = (variant == FL_PLAIN)         ? plain_geom(L, dtype)
               : (variant == FL_DENSE4_FP32) ? fl::make_geom(L, FL_KMAX_C64, 4)
                                             : fl::make_geom(L, FL_KMAX_C64, 6);
-    c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4);
+    c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4, kAdjLowBits);
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
     c->cover_rdm = fl::plan_cover(c->geom_rdm);
@@ -1147,7 +1156,7 @@ int fl_xyz_generators(int L, double* gens_out) {
 int fl_tile_map(int L, int dtype, int h, uint64_t* out) {
     if (dtype != FL_C64 && dtype != FL_C128) return fail(FL_EINVAL, "bad dtype");
     if (L < 2 || L > 24 || !out) return fail(FL_EINVAL, "bad argument");
-    const fl_geom g = fl::make_geom(L, kmax_of(dtype), 4);
+    const fl_geom g = plain_geom(L, dtype);
     if (g.W > 0 && (h < g.C || h + g.W > L)) return fail(FL_EINVAL, "window out of range");
     if (g.W == 0) h = g.C;
     const uint64_t nt = 1ull << (L - g.K);
@@ -1206,16 +1215,15 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     std::vector<fl_pass> plan;
     fl_geom g;
     if (kind == 0) {
-        g = fl::make_geom(L, kmax_of(dtype), dtype == FL_C64 ? FL_SWEEP_R_C64 : 4);
+        g = plain_geom(L, dtype);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
-        const int mg = kind == 5 ? FL_WIN4_MAX_GROUPS : FL_MAX_GROUPS;
-        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
-        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass, nullptr, mg);
+        if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, dagger != 0, false, kMaxGatesPerPass);
+        if (r > 0) pr = fl::plan_sweep(g, (int)r, dagger != 0, false, kMaxGatesPerPass);
         for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
         plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 1) {
-        g = fl::make_geom(L, FL_KMAX_ADJ, 4);
+        g = fl::make_geom(L, FL_KMAX_ADJ, 4, kAdjLowBits);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
         if (q > 0) pb = fl::plan_sweep(g, kPlanBlock, true, true, kMaxGatesPerPass);

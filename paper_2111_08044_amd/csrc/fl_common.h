@@ -42,6 +42,9 @@
 #ifndef FL_SWEEP_NT_C64
 #define FL_SWEEP_NT_C64 256  // threads per workgroup of the complex64 full-tile sweep
 #endif
+#ifndef FL_SWEEP_LOWBITS_C64
+#define FL_SWEEP_LOWBITS_C64 4  // C of the complex64 sweep: 16-amplitude (128-byte) runs, a 9-bit window
+#endif
 #ifndef FL_SWEEP_R_C64
 #define FL_SWEEP_R_C64 5     // register bits per group of the complex64 sweep
 #endif

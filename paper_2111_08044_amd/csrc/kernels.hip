@@ -438,11 +438,12 @@ __device__ __forceinline__ uint32_t sweep_swz(uint32_t j) {
     else return fl_swz(j);
 }
 
-template <typename T, int R, int KT, int NT>
+template <typename T, int R, int KT, int NT, int CL>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_sweep_tiles(typename CT<T>::c* __restrict__ psi,
                                                     const T* __restrict__ gates, int W, fl_pass pd) {
     typedef typename CT<T>::c cplx;
-    constexpr int C = FL_LOWBITS;
+    constexpr int C = CL;
+    static_assert(C >= FL_DIRECT_MIN_U0, "direct register transfers need 2^FL_DIRECT_MIN_U0 contiguous amplitudes");
     constexpr int K = KT;
     constexpr int SUB = (1 << (K - R)) / NT;
     static_assert(SUB >= 1, "tile too small for the workgroup");
@@ -2156,8 +2157,9 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         float2* p = (float2*)psi;
         const float* G = (const float*)gates;
         if (g.K == FL_KMAX_C64 && g.W > 0) {
-            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), grid,
-                               dim3(FL_SWEEP_NT_C64), 0, s, p, G, g.W, pd);
+            if (g.C != FL_SWEEP_LOWBITS_C64) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64, FL_SWEEP_LOWBITS_C64>),
+                               grid, dim3(FL_SWEEP_NT_C64), 0, s, p, G, g.W, pd);
         } else if (g.R == 5)
             hipLaunchKernelGGL((k_sweep<float, 5, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 4)
@@ -2170,7 +2172,9 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         double2* p = (double2*)psi;
         const double* G = (const double*)gates;
         if (g.K == FL_KMAX_C128 && g.W > 0) {
-            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256>), grid, dim3(256), 0, s, p, G, g.W, pd);
+            if (g.C != FL_LOWBITS) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256, FL_LOWBITS>), grid, dim3(256), 0, s, p, G,
+                               g.W, pd);
         } else if (g.R == 4)
             hipLaunchKernelGGL((k_sweep<double, 4, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 3)

@@ -21,15 +21,15 @@
 
 namespace fl {
 
-fl_geom make_geom(int L, int kmax, int r) {
+fl_geom make_geom(int L, int kmax, int r, int lowbits) {
     fl_geom g;
     g.L = L;
     if (L <= kmax) {
         g.C = L;
         g.W = 0;
     } else {
-        g.C = FL_LOWBITS;
-        g.W = kmax - FL_LOWBITS;
+        g.C = lowbits;
+        g.W = kmax - lowbits;
     }
     g.K = g.C + g.W;
     g.R = std::min(r, g.K);

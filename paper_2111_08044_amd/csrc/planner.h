@@ -6,8 +6,12 @@
 
 namespace fl {
 
-// Tile geometry for a chain of L sites; kmax = tile bits, r = register bits.
-fl_geom make_geom(int L, int kmax, int r);
+// Tile geometry for a chain of L sites; kmax = tile bits, r = register bits,
+// lowbits = C, the contiguous low bits of every tile when L > kmax.  A smaller
+// C leaves a wider window of high bits, which the brickwork's light cones
+// cross in fewer passes; C = 4 still keeps every run of a tile one 128-byte
+// line of complex64 amplitudes.
+fl_geom make_geom(int L, int kmax, int r, int lowbits = FL_LOWBITS);
 
 struct PlanStats {
     long long passes = 0;
