@@ -259,7 +259,7 @@ int fl_host_window_overlaps(const double *Q, const double *G, const int *pos, in
 /* The plan fl_apply_period would run for n periods (kind 0 = sweep,
  * 1 = reverse sweep of the gradient, 2 = energy / density-matrix cover on
  * 12-bit tiles (complex128, and complex64 with L <= 13), 3 = cover used for
- * H0 psi, 4 = dense 6-qubit-window sweep, 5 = dense 4-qubit-window sweep,
+ * H0 psi by a plain-sweep context, 4 = dense 6-qubit-window sweep, 5 = dense 4-qubit-window sweep,
  * 6 = energy / density-matrix cover of complex64 states with L >= 14: 13-bit
  * tiles, bonds packed into 5-bit register groups), flattened as int32:
  * [C, W, R, npasses, {h, ngroups, flags, {u0, nops, {i, gate, slot}*}*}*].

@@ -57,7 +57,7 @@ constexpr size_t kStageBytes = 256 << 10;  // bytes per slot: >= 3 x 4096 comple
 int kmax_of(int dtype) { return dtype == FL_C64 ? FL_KMAX_C64 : FL_KMAX_C128; }
 
 // Geometry of the plain sweep: complex64 on 13-bit tiles with 4 low bits and
-// 5-bit register groups, complex128 on 12-bit tiles with 6 low bits and 4-bit
+// 4-bit register groups, complex128 on 12-bit tiles with 6 low bits and 4-bit
 // groups.
 fl_geom plain_geom(int L, int dtype) {
     return dtype == FL_C64 ? fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64, FL_SWEEP_LOWBITS_C64)
@@ -632,7 +632,7 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->cover_rdm = fl::plan_cover(c->geom_rdm);
     c->use_grp = FL_RDM_GROUPS && dtype == FL_C64 && L > FL_KMAX_C64;
     if (c->use_grp) {
-        c->geom_grp = fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64);
+        c->geom_grp = fl::make_geom(L, FL_KMAX_C64, FL_RDM_R_C64);
         c->cover_grp = fl::plan_cover_groups(c->geom_grp);
     }
     const int nb = L - 1;
@@ -1245,11 +1245,11 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
         for (int64_t i = 0; i < q; ++i) plan.insert(plan.end(), pb.begin(), pb.end());
         plan.insert(plan.end(), pr.begin(), pr.end());
     } else if (kind == 3) {
-        g = fl::make_geom(L, kmax_of(dtype), 4);
+        g = plain_geom(L, dtype);
         plan = fl::plan_cover(g);
     } else if (kind == 6) {
         if (dtype != FL_C64 || L <= FL_KMAX_C64) return fail(FL_EINVAL, "the grouped cover needs complex64 and L >= 14");
-        g = fl::make_geom(L, FL_KMAX_C64, FL_SWEEP_R_C64);
+        g = fl::make_geom(L, FL_KMAX_C64, FL_RDM_R_C64);
         plan = fl::plan_cover_groups(g);
     } else {
         return fail(FL_EINVAL, "kind must be 0..6");

@@ -39,15 +39,21 @@
 #define FL_WIN4_NT 512         // threads of the 4-qubit-window reverse pass (13-bit tiles of two states)
 #define FL_KMAX_RDM 12       // tile bits of the energy / density-matrix reduction
 #define FL_MAX_SLOTS 16      // distinct reduction slots per pass
+#define FL_MAX_GATE_TABLE 66 // gates of the largest chain (L = 34): G_b and G_b^dagger per bond
 #ifndef FL_SWEEP_NT_C64
-#define FL_SWEEP_NT_C64 256  // threads per workgroup of the complex64 full-tile sweep
+#define FL_SWEEP_NT_C64 512  // threads per workgroup of the complex64 full-tile sweep
 #endif
 #ifndef FL_SWEEP_LOWBITS_C64
 #define FL_SWEEP_LOWBITS_C64 4  // C of the complex64 sweep: 16-amplitude (128-byte) runs, a 9-bit window
 #endif
 #ifndef FL_SWEEP_R_C64
-#define FL_SWEEP_R_C64 5     // register bits per group of the complex64 sweep
+#define FL_SWEEP_R_C64 4     // register bits per group of the complex64 sweep
 #endif
+#ifndef FL_SWEEP_LDS_GATES
+#define FL_SWEEP_LDS_GATES 1  // complex64 sweep: gates in vector registers, read from an LDS copy of the table
+#endif
+#define FL_RDM_NT_C64 256    // threads per workgroup of the complex64 bond reduction on 13-bit tiles
+#define FL_RDM_R_C64 5       // register bits per group of that reduction
 #ifndef FL_RDM_GROUPS
 #define FL_RDM_GROUPS 1      // complex64 reductions on 13-bit tiles with register groups (L >= 14)
 #endif

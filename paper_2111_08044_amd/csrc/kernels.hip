@@ -410,6 +410,47 @@ __device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SU
     }
 }
 
+// The same with the gates in vector registers, read from the workgroup's LDS
+// copy of the gate table (lg, 32 floats per gate): FP32 FMAs whose operands
+// all sit in vector registers can issue two per cycle per SIMD on gfx950 when
+// two waves have one ready, where an FMA that reads a scalar register issues
+// alone.  All lanes read the same address, so each 16-byte read is a
+// broadcast.
+template <typename T, int R, int SUB>
+__device__ __forceinline__ void sweep_group_ops_lg(T (&vr)[SUB][1 << R], T (&vi)[SUB][1 << R], const fl_pass& pd,
+                                                   int g, const float* lg) {
+    const int nops = pass_nops(pd, g);
+    // op metadata (bit, gate index) is read with scalar loads one op ahead;
+    // LDS and scalar loads share one wait counter, so the next op's scalar
+    // loads are issued only after this op's gate has arrived from LDS, and
+    // they complete under the op's FMAs.
+    int bit = pass_bit(pd, g, 0), idx = pass_gate(pd, g, 0);
+    auto run = [&](int q) {
+        __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+        const float4* src = reinterpret_cast<const float4*>(lg + 32 * idx);
+        T gv[32];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float4 v = src[k];
+            gv[4 * k] = v.x;
+            gv[4 * k + 1] = v.y;
+            gv[4 * k + 2] = v.z;
+            gv[4 * k + 3] = v.w;
+        }
+        __builtin_amdgcn_s_waitcnt(FL_WAIT_LGKM0);
+        const int i = bit;
+        const int qn = q + 1 < nops ? q + 1 : q;
+        bit = pass_bit(pd, g, qn);
+        idx = pass_gate(pd, g, qn);
+#pragma unroll
+        for (int s = 0; s < SUB; ++s) apply_op_g<T, R>(vr[s], vi[s], i, gv);
+    };
+    for (int q = 0; q < nops; q += 2) {
+        run(q);
+        if (q + 1 < nops) run(q + 1);
+    }
+}
+
 // Full-size tiles (K = KT), one tile per workgroup.  Every thread holds SUB
 // register groups of 2^R amplitudes and applies each gate to all of them; the
 // next gate's matrix is fetched while the current one is applied.
@@ -421,7 +462,8 @@ __device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SU
 // saves one LDS round trip and one barrier at each end of the pass.  Groups
 // starting lower go through the LDS transpose, as every middle group does.
 //
-// LDS slots of the complex64 sweep (13 tile bits, 5 register bits).  Each run
+// LDS slots of 13-bit complex64 tiles with 5-bit register groups (the bond
+// reduction's layout, and the sweep's with 256-thread workgroups).  Each run
 // of 16 lanes of an 8-byte LDS access must hit 16 distinct slots modulo 16.
 // In a register group with first bit u0 the 16 lanes vary the four lowest
 // tile bits outside [u0, u0 + 5): bits 5..8 for u0 = 0, {0, 6, 7, 8} for
@@ -431,17 +473,24 @@ __device__ __forceinline__ void sweep_group_ops(T (&vr)[SUB][1 << R], T (&vi)[SU
 // loads (lanes varying bits 1..4) conflict-free.  Like fl_swz it is linear
 // over XOR, its added term depends on none of bits 0..3, and it leaves every
 // bit from 9 up alone.
-// The complex128 sweep (12 tile bits, 4 register bits) keeps fl_swz.
-template <typename T>
+// Sweeps with 4-bit register groups (complex64 with 512-thread workgroups,
+// complex128) keep fl_swz, which serves every u0 of a 4-bit group.
+template <typename T, int R>
 __device__ __forceinline__ uint32_t sweep_swz(uint32_t j) {
-    if constexpr (sizeof(T) == 4) return j ^ ((j >> 5) & 15u) ^ ((j >> 4) & 1u);
+    if constexpr (sizeof(T) == 4 && R == 5) return j ^ ((j >> 5) & 15u) ^ ((j >> 4) & 1u);
     else return fl_swz(j);
 }
 
-template <typename T, int R, int KT, int NT, int CL>
+template <typename T, int R, int KT, int NT, int CL, bool LG>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256))) void k_sweep_tiles(typename CT<T>::c* __restrict__ psi,
-                                                    const T* __restrict__ gates, int W, fl_pass pd) {
+                                                    const T* __restrict__ gates, int W, fl_pass pd, int ngates) {
     typedef typename CT<T>::c cplx;
+    static_assert(!LG || sizeof(T) == 4, "LDS gate table: complex64 only");
+    __shared__ __attribute__((aligned(16))) float lg[LG ? FL_MAX_GATE_TABLE * 32 : 4];
+    if constexpr (LG) {
+        const float4* src = reinterpret_cast<const float4*>(gates);
+        for (int t = threadIdx.x; t < ngates * 8; t += NT) reinterpret_cast<float4*>(lg)[t] = src[t];
+    }
     constexpr int C = CL;
     static_assert(C >= FL_DIRECT_MIN_U0, "direct register transfers need 2^FL_DIRECT_MIN_U0 contiguous amplitudes");
     constexpr int K = KT;
@@ -462,7 +511,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     // LDS slot of element j + s APL NT is sweep_swz(j) + s APL NT (the
     // swizzle only mixes bits 0..8), and sweep_swz(j + 1) = sweep_swz(j) ^ 1
     // for even j.
-    const uint32_t l0 = sweep_swz<T>(APL * threadIdx.x);
+    const uint32_t l0 = sweep_swz<T, R>(APL * threadIdx.x);
     const bool din = ng > 0 && pass_u0(pd, 0) >= FL_DIRECT_MIN_U0;
     const bool dout = ng > 0 && pass_u0(pd, ng - 1) >= FL_DIRECT_MIN_U0;
 
@@ -498,11 +547,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     auto lds_addrs = [&](int u0) {
         uint32_t bk[R];
 #pragma unroll
-        for (int k = 0; k < R; ++k) bk[k] = sweep_swz<T>(1u << (u0 + k)) * (uint32_t)sizeof(cplx);
+        for (int k = 0; k < R; ++k) bk[k] = sweep_swz<T, R>(1u << (u0 + k)) * (uint32_t)sizeof(cplx);
 #pragma unroll
         for (int s = 0; s < SUB; ++s) {
             b0[s] = fl_spread(threadIdx.x + s * NT, u0, R);
-            la[s][0] = sweep_swz<T>(b0[s]) * (uint32_t)sizeof(cplx);
+            la[s][0] = sweep_swz<T, R>(b0[s]) * (uint32_t)sizeof(cplx);
 #pragma unroll
             for (int m = 1; m < (1 << R); ++m) la[s][m] = la[s][m & (m - 1)] ^ bk[__builtin_ctz(m)];
         }
@@ -565,16 +614,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     // the first gate of the pass (later groups find theirs fetched by the
     // previous group's op loop)
     T gx[32];
-    if (ng > 0) {
+    if (!LG && ng > 0) {
         const T* G = gates + 32 * pass_gate(pd, 0, 0);
 #pragma unroll
         for (int k = 0; k < 32; ++k) gx[k] = G[k];
     }
+    if (LG && din) __syncthreads();   // the gate table (other paths pass a barrier after the tile load)
     for (int g = 0; g < ng; ++g) {
         const int u0 = pass_u0(pd, g);
         if (g > 0 || din) lds_addrs(u0);
         if (g > 0) lds_to_regs();
-        sweep_group_ops<T, R, SUB>(vr, vi, pd, g, gates, gx);
+        if constexpr (LG)
+            sweep_group_ops_lg<T, R, SUB>(vr, vi, pd, g, lg);
+        else
+            sweep_group_ops<T, R, SUB>(vr, vi, pd, g, gates, gx);
         if (g == ng - 1 && dout) break;
         regs_to_lds();
         __syncthreads();
@@ -1000,7 +1053,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
     // sweep_swz(j) + s 2 NT, and sweep_swz(j + 1) = sweep_swz(j) ^ 1
     const uint64_t toff = fl_tile_offset(2 * threadIdx.x, C, h);
     const uint64_t tstride = (uint64_t)((2 * NT) >> C) << h;
-    const uint32_t l0 = sweep_swz<float>(2 * threadIdx.x);
+    const uint32_t l0 = sweep_swz<float, R>(2 * threadIdx.x);
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const float2* src = psi + fl_tile_base(tile, C, W, h) + toff;
         float4 v[ITER];
@@ -1032,9 +1085,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT * 2 / 256
             // slot(b0 | m << u0) = slot(b0) ^ XOR of the slots of m's set bits
             uint32_t bk[R];
 #pragma unroll
-            for (int k = 0; k < R; ++k) bk[k] = sweep_swz<float>(1u << (u0 + k)) * 8u;
+            for (int k = 0; k < R; ++k) bk[k] = sweep_swz<float, R>(1u << (u0 + k)) * 8u;
             uint32_t la[1 << R];
-            la[0] = sweep_swz<float>(fl_spread(threadIdx.x, u0, R)) * 8u;
+            la[0] = sweep_swz<float, R>(fl_spread(threadIdx.x, u0, R)) * 8u;
 #pragma unroll
             for (int m = 1; m < (1 << R); ++m) la[m] = la[m & (m - 1)] ^ bk[__builtin_ctz(m)];
             double vr[1 << R], vi[1 << R];
@@ -2158,8 +2211,10 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         const float* G = (const float*)gates;
         if (g.K == FL_KMAX_C64 && g.W > 0) {
             if (g.C != FL_SWEEP_LOWBITS_C64) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64, FL_SWEEP_LOWBITS_C64>),
-                               grid, dim3(FL_SWEEP_NT_C64), 0, s, p, G, g.W, pd);
+            if (2 * (g.L - 1) > FL_MAX_GATE_TABLE) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(
+                (k_sweep_tiles<float, FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64, FL_SWEEP_LOWBITS_C64, FL_SWEEP_LDS_GATES != 0>), grid,
+                dim3(FL_SWEEP_NT_C64), 0, s, p, G, g.W, pd, 2 * (g.L - 1));
         } else if (g.R == 5)
             hipLaunchKernelGGL((k_sweep<float, 5, 0, FL_KMAX_C64>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 4)
@@ -2173,8 +2228,8 @@ hipError_t launch_sweep(int dtype, const fl_geom& g, void* psi, const void* gate
         const double* G = (const double*)gates;
         if (g.K == FL_KMAX_C128 && g.W > 0) {
             if (g.C != FL_LOWBITS) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256, FL_LOWBITS>), grid, dim3(256), 0, s, p, G,
-                               g.W, pd);
+            hipLaunchKernelGGL((k_sweep_tiles<double, 4, FL_KMAX_C128, 256, FL_LOWBITS, false>), grid, dim3(256), 0, s,
+                               p, G, g.W, pd, 0);
         } else if (g.R == 4)
             hipLaunchKernelGGL((k_sweep<double, 4, 0, FL_KMAX_C128>), grid, block, 0, s, p, G, g.C, g.W, pd);
         else if (g.R == 3)
@@ -2210,8 +2265,8 @@ hipError_t launch_rdm(int dtype, const fl_geom& g, const void* psi, const fl_pas
 
 hipError_t launch_rdm_groups(const fl_geom& g, const void* psi, const fl_pass& pd, double* partials, int grid,
                              int nslot, hipStream_t s) {
-    if (g.K != FL_KMAX_C64 || g.R != FL_SWEEP_R_C64 || g.W == 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_rdm_groups<FL_SWEEP_R_C64, FL_KMAX_C64, FL_SWEEP_NT_C64>), dim3(grid), dim3(FL_SWEEP_NT_C64), 0,
+    if (g.K != FL_KMAX_C64 || g.R != FL_RDM_R_C64 || g.W == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_rdm_groups<FL_RDM_R_C64, FL_KMAX_C64, FL_RDM_NT_C64>), dim3(grid), dim3(FL_RDM_NT_C64), 0,
                        s, (const float2*)psi, g.W, ntiles_of(g), pd, partials, nslot);
     return hipGetLastError();
 }
