@@ -49,6 +49,7 @@ constexpr int kMaxGatesPerPass = 96;  // cap on gates the planner puts in one pa
 constexpr int kReduceGrid = 2048;     // workgroups of the persistent reduction kernels
 constexpr int kAdjGrid = 1024;        // workgroups of the persistent reverse pass
 constexpr int kAdjLowBits = 4;       // low tile bits of the reverse pass (its kernel takes C at run time)
+constexpr int kDense6LowBits = 4;    // low tile bits of the 6-qubit-window forms (their kernel takes C at run time)
 constexpr int kWin4Grid = 256;        // workgroups of the 4-qubit-window reverse pass (one per CU)
 constexpr int kMinNoallocGrid = 256;  // fewest reduction workgroups fl_expect_energy_noalloc runs
 constexpr int kStageSlots = 8;        // pinned host staging slots for uploads
@@ -433,7 +434,7 @@ int run_reverse(fl_ctx* c, void* psi, void* lam, int64_t n) {
 // The 4-qubit-window form (complex64, full 13-bit tiles) replays its own
 // forward windows backwards on the matrix cores (k_adjoint_win4).
 bool use_win4_reverse(const fl_ctx* c) {
-    return c->dtype == FL_C64 && c->variant == FL_DENSE4_FP32 && c->geom.R == 4 && c->geom.C == FL_LOWBITS &&
+    return c->dtype == FL_C64 && c->variant == FL_DENSE4_FP32 && c->geom.R == 4 && c->geom.C == FL_DENSE4_LOWBITS &&
            c->geom.C + c->geom.W == FL_KMAX_C64;
 }
 
@@ -624,8 +625,8 @@ int fl_create(fl_ctx** ctx, int L, int dtype, int variant, void* hip_stream) {
     c->dev = dev;
     c->stream = (hipStream_t)hip_stream;
     c->geom = (variant == FL_PLAIN)         ? plain_geom(L, dtype)
-              : (variant == FL_DENSE4_FP32) ? fl::make_geom(L, FL_KMAX_C64, 4)
-                                            : fl::make_geom(L, FL_KMAX_C64, 6);
+              : (variant == FL_DENSE4_FP32) ? fl::make_geom(L, FL_KMAX_C64, 4, FL_DENSE4_LOWBITS)
+                                            : fl::make_geom(L, FL_KMAX_C64, 6, kDense6LowBits);
     c->geom_adj = fl::make_geom(L, FL_KMAX_ADJ, 4, kAdjLowBits);
     c->geom_rdm = fl::make_geom(L, FL_KMAX_RDM, 2);
     c->cover = fl::plan_cover(c->geom);
@@ -1236,7 +1237,8 @@ int fl_plan_query(int L, int dtype, int kind, int64_t n, int dagger, int32_t* bu
     } else if (kind == 4 || kind == 5) {
         if (dtype != FL_C64 || L < (kind == 4 ? 11 : FL_KMAX_C64))
             return fail(FL_EINVAL, "dense plans need complex64 and L >= 11 (6-qubit) or 13 (4-qubit windows)");
-        g = fl::make_geom(L, FL_KMAX_C64, kind == 4 ? 6 : 4);
+        g = kind == 4 ? fl::make_geom(L, FL_KMAX_C64, 6, kDense6LowBits)
+                      : fl::make_geom(L, FL_KMAX_C64, 4, FL_DENSE4_LOWBITS);
         const int64_t q = n / kPlanBlock, r = n % kPlanBlock;
         std::vector<fl_pass> pb, pr;
         const int mg = kind == 5 ? FL_WIN4_MAX_GROUPS : FL_MAX_GROUPS;

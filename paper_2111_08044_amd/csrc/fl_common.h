@@ -57,6 +57,9 @@
 #ifndef FL_RDM_GROUPS
 #define FL_RDM_GROUPS 1      // complex64 reductions on 13-bit tiles with register groups (L >= 14)
 #endif
+#ifndef FL_DENSE4_LOWBITS
+#define FL_DENSE4_LOWBITS 4  // C of the 4-qubit-window form (forward and reverse pass)
+#endif
 #ifndef FL_DENSE4_NW
 #define FL_DENSE4_NW 4       // waves per workgroup of the 4-qubit-window MFMA kernel
 #endif

@@ -1545,7 +1545,7 @@ __global__ __launch_bounds__(FL_WIN4_NT) __attribute__((amdgpu_waves_per_eu(2)))
     float2* __restrict__ psi, float2* __restrict__ lam, const float4* __restrict__ mats, int W, uint32_t ntiles,
     fl_pass pd, double* __restrict__ Qpart) {
     constexpr int K = FL_KMAX_C64;
-    constexpr int C = FL_LOWBITS;
+    constexpr int C = FL_DENSE4_LOWBITS;
     constexpr int NT = FL_WIN4_NT;
     constexpr int NW = NT / 64;
     constexpr int KC = K - 4;                   // column bits of a group
@@ -2079,7 +2079,7 @@ template <int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 2))) void k_dense4(
     float2* __restrict__ psi, const float4* __restrict__ mats, int W, fl_pass pd) {
     constexpr int K = 13;
-    constexpr int C = FL_LOWBITS;
+    constexpr int C = FL_DENSE4_LOWBITS;
     constexpr int NB = 16 / NW;                  // 32-column blocks per wave (512 columns per tile)
     constexpr int WB = __builtin_ctz(NW);        // column bits that name the wave
     __shared__ __attribute__((aligned(16))) float2 lds[1 << K];
@@ -2381,7 +2381,7 @@ hipError_t launch_adjoint(int dtype, const fl_geom& g, void* psi, void* lam, con
 
 hipError_t launch_adjoint_win4(const fl_geom& g, void* psi, void* lam, const void* mats, const fl_pass& pd,
                                double* Qpart, int grid, double* Qsum, hipStream_t s) {
-    if (g.K != FL_KMAX_C64 || g.R != 4 || g.C != FL_LOWBITS || g.C + g.W != FL_KMAX_C64 ||
+    if (g.K != FL_KMAX_C64 || g.R != 4 || g.C != FL_DENSE4_LOWBITS || g.C + g.W != FL_KMAX_C64 ||
         pd.ngroups > FL_WIN4_MAX_GROUPS || grid < 1)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_adjoint_win4, dim3(grid), dim3(FL_WIN4_NT), 0, s, (float2*)psi, (float2*)lam,
@@ -2402,14 +2402,14 @@ hipError_t launch_dense4(const fl_geom& g, void* psi, const void* mats, const fl
     if (g.C + g.W != 13) return hipErrorInvalidValue;
     if (g.W == 0) {
         // a single 13-bit tile (L = 13): the same amplitudes as low bits
-        // [0, 6) plus the window [6, 13), the kernel's fixed geometry
+        // [0, C) plus the window [C, 13), the kernel's fixed geometry
         fl_pass p = pd;
-        p.h = FL_LOWBITS;
+        p.h = FL_DENSE4_LOWBITS;
         hipLaunchKernelGGL(k_dense4<FL_DENSE4_NW>, dim3(1), dim3(64 * FL_DENSE4_NW), 0, s, (float2*)psi,
-                           (const float4*)mats, 13 - FL_LOWBITS, p);
+                           (const float4*)mats, 13 - FL_DENSE4_LOWBITS, p);
         return hipGetLastError();
     }
-    if (g.C != FL_LOWBITS) return hipErrorInvalidValue;
+    if (g.C != FL_DENSE4_LOWBITS) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_dense4<FL_DENSE4_NW>, dim3(ntiles_of(g)), dim3(64 * FL_DENSE4_NW), 0, s, (float2*)psi,
                        (const float4*)mats, g.W, pd);
     return hipGetLastError();
