@@ -489,14 +489,15 @@ def test_autograd_function_matches_oracle():
 
 # ----------------------------------------------------------------- measurement probe
 
-def test_fma_probe_computes_its_recurrence():
-    """The FMA-loop probe behind the bench's measured ceiling runs the
-    recurrence x <- 0.999 x + 0.001 it states (closed form in FP64)."""
+@pytest.mark.parametrize("name", ["flp_fma_loop", "flp_fma_loop_v"])
+def test_fma_probe_computes_its_recurrence(name):
+    """The FMA-loop probes behind the bench's measured ceilings run the
+    recurrence x <- 0.999 x + 0.001 they state (closed form in FP64)."""
     import ctypes
     path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                         "paper_2111_08044_amd", "libflprobe.so")
     lib = ctypes.CDLL(path)
-    f = lib.flp_fma_loop
+    f = getattr(lib, name)
     f.restype = ctypes.c_int
     f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     blocks, iters = 3, 500

@@ -46,17 +46,17 @@ def test_probe_library_exports_and_validates():
         pytest.skip("libflprobe.so not built")
     with open(os.path.join(ROOT, "paper_2111_08044_amd", "csrc", "probe.h")) as f:
         names = set(re.findall(r"^\s*int\s*(flp_\w+)\s*\(", f.read(), re.M))
-    assert names == {"flp_fma_loop"}
+    assert names == {"flp_fma_loop", "flp_fma_loop_v"}
     lib = ctypes.CDLL(path)
     for n in names:
         assert hasattr(lib, n), n
-    f = lib.flp_fma_loop
-    f.restype = ctypes.c_int
-    f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
-    assert f(None, 8, 10, None) == -1
-    assert f(ctypes.c_void_p(256), 0, 10, None) == -1
-    assert f(ctypes.c_void_p(256), 8, 0, None) == -1
-    assert f(ctypes.c_void_p(256), (1 << 20) + 1, 10, None) == -1
+        f = getattr(lib, n)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        assert f(None, 8, 10, None) == -1
+        assert f(ctypes.c_void_p(256), 0, 10, None) == -1
+        assert f(ctypes.c_void_p(256), 8, 0, None) == -1
+        assert f(ctypes.c_void_p(256), (1 << 20) + 1, 10, None) == -1
 
 
 def test_create_without_device_fails_cleanly():
