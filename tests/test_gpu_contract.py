@@ -42,9 +42,10 @@ def _model(L, seed=fin.DEFAULT_SEED, T=0.25):
 
 
 # Bond windows at L = 30 (bond b acts on bits L-2-b, L-1-b): the top bits,
-# two mid-chain windows, and one across the low-bit boundary (bits 1..7, so
-# bond 23 straddles bits 5 and 6, the edge between a tile's contiguous low
-# bits and its high window).
+# two mid-chain windows, and one across the low-bit boundaries (bits 1..7:
+# bond 25 straddles bits 3 and 4, the edge between the complex64 sweep's 4
+# contiguous low tile bits and its high window; bond 23 straddles bits 5 and
+# 6, the same edge for the 6-low-bit tiles of the energy reduction).
 L30_WINDOWS = [(0, 5), (7, 12), (14, 19), (22, 27)]
 
 
