@@ -452,8 +452,11 @@ __device__ __forceinline__ void sweep_group_ops_lg(T (&vr)[SUB][1 << R], T (&vi)
 }
 
 // Full-size tiles (K = KT), one tile per workgroup.  Every thread holds SUB
-// register groups of 2^R amplitudes and applies each gate to all of them; the
-// next gate's matrix is fetched while the current one is applied.
+// register groups of 2^R amplitudes and applies each gate to all of them.
+// With LG (complex64) each op reads its gate from the workgroup's LDS copy of
+// the gate table into vector registers; otherwise (complex128) the next
+// gate's matrix is fetched into scalar registers while the current one is
+// applied.
 //
 // The first group is loaded straight from HBM into its register layout, and
 // the last group stored straight back, when the group's lowest bit u0 is at
