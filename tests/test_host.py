@@ -272,15 +272,31 @@ def test_grouped_energy_cover_needs_complex64_and_long_chains():
 
 
 def test_plan_statistics_L30():
-    """The fused plan at L = 30 complex64 needs few passes per period: with the
-    one-step lookahead of the planner, 31 passes for a 16-period block and 20
-    for the 10 periods between two energy readouts (the plain greedy choice
-    took 33 and 22)."""
-    for n, most in ((16, 31), (10, 20)):
+    """The fused plan at L = 30 complex64 needs few passes per period: on
+    13-bit tiles with 4 low bits (a 9-bit window), 20 passes for a 16-period
+    block and 14 for the 10 periods between two energy readouts (31 and 20
+    with 6 low bits)."""
+    for n, most in ((16, 20), (10, 14)):
         _, _, _, passes = pt.parse_plan(fl.fl_plan_query(30, "c64", 0, n, False))
         assert len(passes) <= most, (n, len(passes))
         gates = sum(len(ops) for _, _, groups in passes for _, ops in groups)
         assert gates == 29 * n
+
+
+@pytest.mark.parametrize("kind,dtype,geom", [
+    (0, "c64", (4, 9, 4)),    # plain sweep: 4 low bits, 4-bit groups (512-thread workgroups)
+    (0, "c128", (6, 6, 4)),
+    (1, "c64", (4, 8, 4)),    # gradient reverse pass: 12-bit tiles with 4 low bits
+    (3, "c64", (4, 9, 4)),    # H0 psi cover of the plain geometry
+    (4, "c64", (4, 9, 6)),    # 6-qubit windows
+    (5, "c64", (4, 9, 4)),    # 4-qubit windows (forward and reverse pass)
+    (6, "c64", (6, 7, 5)),    # energy reduction: 6 low bits, 5-bit groups
+])
+def test_tile_geometries(kind, dtype, geom):
+    """The tile geometry (C low bits, W window bits, R register bits) each
+    kind of plan uses at L = 24; the kernels are built for exactly these."""
+    C, W, R, _ = pt.parse_plan(fl.fl_plan_query(24, dtype, kind, 2, kind == 1))
+    assert (C, W, R) == geom
 
 
 # ------------------------------------------------------------ dense windows
